@@ -1,0 +1,231 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+a library routine (numpy.corrcoef), closed forms, invariants of Eq. (1),
+hand-worked fixtures, and brute force.  CPU only."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_textbook():
+    vals = {}
+    with open(os.path.join(GOLDEN, "pearson_textbook.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, *rest = line.split()
+            vals[k] = np.array([float(t) for t in rest])
+    return vals
+
+
+def test_textbook_example(oracle_mod):
+    v = _read_textbook()
+    X = np.stack([v["u"], v["v"]])
+    r = oracle_mod.pearson_packed(X)
+    assert r.shape == (1,)
+    assert abs(r[0] - v["r"][0]) <= 1e-15
+    assert abs(r[0] - np.sqrt(0.6)) <= 1e-15
+
+
+@pytest.mark.parametrize("l", [2, 3, 17, 256])
+@pytest.mark.parametrize("n", [2, 5, 64])
+def test_vs_numpy_corrcoef(oracle_mod, n, l):
+    rng = np.random.default_rng(100 + n * 7 + l)
+    X = rng.standard_normal((n, l)) * rng.uniform(0.1, 10, (n, 1)) + rng.uniform(-5, 5, (n, 1))
+    r = oracle_mod.pearson_packed(X)
+    C = np.corrcoef(X)
+    iu = np.triu_indices(n, 1)
+    assert r.shape == (n * (n - 1) // 2,)
+    np.testing.assert_allclose(r, C[iu], rtol=0, atol=1e-12)
+
+
+def test_packed_order_matches_row_major_upper(oracle_mod):
+    # a permutation-free check of the output order: distinct rows give
+    # distinct r, and position t must hold the pair of the t-th cell
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((9, 40))
+    r = oracle_mod.pearson_packed(X)
+    t = 0
+    for i in range(9):
+        for j in range(i + 1, 9):
+            assert r[t] == oracle_mod.pearson_pairs(X, [i], [j])[0]
+            t += 1
+
+
+def test_invariants(oracle_mod):
+    rng = np.random.default_rng(11)
+    l = 300
+    u = rng.standard_normal(l)
+    v = rng.standard_normal(l)
+    X = np.stack([u, u.copy(), -u, 2.5 * u - 7.0, -0.3 * u + 1.0, v, 4.0 * v + 3.0])
+    r = oracle_mod.pearson_pairs
+    assert r(X, [0], [1])[0] == 1.0                       # r(u,u) = 1
+    assert abs(r(X, [0], [2])[0] + 1.0) <= 1e-15          # r(u,-u) = -1
+    assert abs(r(X, [0], [3])[0] - 1.0) <= 1e-13          # positive affine
+    assert abs(r(X, [0], [4])[0] + 1.0) <= 1e-13          # negative slope
+    # symmetry, bit for bit
+    assert r(X, [0], [5])[0] == r(X, [5], [0])[0]
+    # invariance of r(u, v) under a positive affine map of v
+    assert abs(r(X, [0], [5])[0] - r(X, [0], [6])[0]) <= 1e-13
+    # bounded
+    Y = rng.standard_normal((40, 8))
+    assert np.all(np.abs(oracle_mod.pearson_packed(Y)) <= 1.0)
+
+
+def test_constant_and_nonfinite_rows_give_nan(oracle_mod):
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((4, 10))
+    X[1] = 3.25
+    X[3, 4] = np.nan
+    r = oracle_mod.pearson_packed(X)
+    # pairs: (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
+    assert np.isnan(r[0]) and np.isnan(r[2]) and np.isnan(r[3]) and np.isnan(r[4])
+    assert np.isnan(r[5])
+    assert np.isfinite(r[1])
+
+
+@pytest.mark.parametrize("a,c", [(1.0, 0.0), (0.6, 0.8), (-2.0, 1.0), (0.1, 3.0), (-0.5, -0.5)])
+def test_closed_form_planted_pair(oracle_mod, a, c):
+    # u and w centred, unit length and orthogonal; v = a*u + c*w + b has
+    # r(u, v) = a / sqrt(a^2 + c^2) exactly.
+    rng = np.random.default_rng(21)
+    l = 257
+    u = rng.standard_normal(l)
+    u -= u.mean()
+    u /= np.linalg.norm(u)
+    w = rng.standard_normal(l)
+    w -= w.mean()
+    w -= (w @ u) * u
+    w -= w.mean()
+    w /= np.linalg.norm(w)
+    v = a * u + c * w + 0.37
+    r = oracle_mod.pearson_pairs(np.stack([u, v]), [0], [1])[0]
+    assert abs(r - a / np.hypot(a, c)) <= 1e-13
+
+
+def test_transform_pins(oracle_mod):
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((30, 101)) * 3.0 + 11.0
+    U, mean, m2 = oracle_mod.transform(X)
+    np.testing.assert_allclose(mean, X.mean(axis=1), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(m2, ((X - X.mean(axis=1, keepdims=True)) ** 2).sum(axis=1),
+                               rtol=1e-13)
+    np.testing.assert_allclose(np.linalg.norm(U, axis=1), 1.0, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(U.sum(axis=1), 0.0, rtol=0, atol=1e-13)
+    # Eq. (5): after Eq. (4) the dot product of two rows is Eq. (1)
+    G = U @ U.T
+    iu = np.triu_indices(30, 1)
+    np.testing.assert_allclose(G[iu], oracle_mod.pearson_packed(X), rtol=0, atol=1e-14)
+
+
+def test_transform_degenerate_row_is_nan(oracle_mod):
+    X = np.ones((2, 5))
+    X[1] = [1, 2, 3, 4, 5]
+    U, mean, m2 = oracle_mod.transform(X)
+    assert m2[0] == 0.0 and np.all(np.isnan(U[0]))
+    assert np.all(np.isfinite(U[1]))
+
+
+def _golden_jobmap():
+    tab = {}
+    cur = None
+    with open(os.path.join(GOLDEN, "jobmap_n4.txt")) as f:
+        for line in f:
+            s = line.strip()
+            if not s or s.startswith("#"):
+                continue
+            if s in ("inclusive", "exclusive"):
+                cur = s
+                tab[cur] = []
+                continue
+            tab[cur].append(tuple(int(t) for t in s.split()))
+    return tab
+
+
+def test_enumeration_golden(oracle_mod):
+    tab = _golden_jobmap()
+    for name, diag in (("inclusive", True), ("exclusive", False)):
+        ys, xs = oracle_mod.enumerate_upper(4, diag)
+        got = [(i, int(y), int(x)) for i, (y, x) in enumerate(zip(ys, xs))]
+        assert got == tab[name]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 257])
+def test_enumeration_brute_force(oracle_mod, n):
+    for diag in (True, False):
+        ys, xs = oracle_mod.enumerate_upper(n, diag)
+        want = [(y, x) for y in range(n) for x in range(y if diag else y + 1, n)]
+        assert list(zip(ys.tolist(), xs.tolist())) == want
+        # F_n(n) = n(n+1)/2 cells with the diagonal, n(n-1)/2 without
+        assert len(ys) == (n * (n + 1) // 2 if diag else n * (n - 1) // 2)
+
+
+def test_permcounts_identity_and_repeated(oracle_mod):
+    rng = np.random.default_rng(4)
+    n, l, P = 12, 33, 20
+    X = rng.standard_normal((n, l))
+    I, J = np.triu_indices(n, 1)
+    ident = np.tile(np.arange(l, dtype=np.int32), (P, 1))
+    counts, gap = oracle_mod.permcounts(X, ident, I, J)
+    assert np.all(counts == P) and np.all(gap == 0.0)
+    one = rng.permutation(l).astype(np.int32)
+    counts, _ = oracle_mod.permcounts(X, np.tile(one, (P, 1)), I, J)
+    assert set(np.unique(counts).tolist()) <= {0, P}
+
+
+def test_permcounts_vs_numpy(oracle_mod):
+    rng = np.random.default_rng(9)
+    n, l, P = 10, 24, 50
+    X = rng.standard_normal((n, l))
+    perms = np.stack([rng.permutation(l) for _ in range(P)]).astype(np.int32)
+    I, J = np.triu_indices(n, 1)
+    counts, gap = oracle_mod.permcounts(X, perms, I, J)
+    for q, (i, j) in enumerate(zip(I, J)):
+        robs = abs(np.corrcoef(X[i], X[j])[0, 1])
+        rp = np.array([abs(np.corrcoef(X[i], X[j][perms[p]])[0, 1]) for p in range(P)])
+        want = int(np.sum(rp >= robs))
+        if gap[q] > 1e-10:
+            assert counts[q] == want
+        assert abs(gap[q] - np.min(np.abs(rp - robs))) <= 1e-12
+
+
+def test_permcounts_nan_pair(oracle_mod):
+    X = np.random.default_rng(1).standard_normal((3, 8))
+    X[2] = 1.0
+    perms = np.stack([np.arange(8), np.arange(8)[::-1]]).astype(np.int32)
+    counts, _ = oracle_mod.permcounts(X, perms, [0, 0, 1], [1, 2, 2])
+    assert counts[1] == -1 and counts[2] == -1 and counts[0] >= 1
+
+
+def test_edges_vs_numpy(oracle_mod):
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((60, 20))
+    X[7] = 0.9 * X[3] + 0.1 * rng.standard_normal(20)
+    X[40] = -X[11] + 0.05 * rng.standard_normal(20)
+    thr = 0.6
+    EI, EJ, ER = oracle_mod.edges(X, thr)
+    C = np.corrcoef(X)
+    iu = np.triu_indices(60, 1)
+    keep = np.abs(C[iu]) >= thr
+    near = np.abs(np.abs(C[iu]) - thr) <= 1e-12
+    want = set(zip(iu[0][keep & ~near].tolist(), iu[1][keep & ~near].tolist()))
+    got = set(zip(EI.tolist(), EJ.tolist()))
+    assert want <= got and len(got - want) <= int(near.sum())
+    assert (3, 7) in got and (11, 40) in got
+    # (i, j) order
+    order = np.lexsort((EJ, EI))
+    assert np.all(order == np.arange(len(EI)))
+
+
+def test_planted_pairs_follow_model(oracle_mod):
+    X, pl = workloads.config1()
+    assert X.shape == (2000, 256) and X.dtype == np.float64
+    r = oracle_mod.pearson_pairs(X, pl.u, pl.v)
+    rho = pl.a / np.sqrt(pl.a ** 2 + 0.01)
+    # sampling error of r around rho is about (1 - rho^2)/sqrt(l)
+    assert np.all(np.abs(r - rho) <= 6 * (1 - rho ** 2) / np.sqrt(256) + 1e-3)
+    assert len(set(pl.u.tolist()) | set(pl.v.tolist())) == 40
