@@ -1,0 +1,251 @@
+/*
+ * pcc.h - all-pairs Pearson correlation on AMD Instinct MI355X (gfx950).
+ *
+ * The C ABI of libpcc.so.  Every argument is a plain pointer or integer;
+ * device buffers are passed as device pointers, streams as hipStream_t cast
+ * to void* (NULL means the default stream).  The caller owns every buffer.
+ * No entry point allocates device memory while computing; the only device
+ * allocations the library ever makes are the hipGraph objects of a batch
+ * plan (pcc_batch_plan_create).
+ *
+ * Method (Liu, Pan and Aluru, "Parallel pairwise correlation computation on
+ * Intel Xeon Phi clusters"):
+ *   Eq. (1)   r(u,v) = sum (u-ub)(v-vb) / sqrt(sum (u-ub)^2 * sum (v-vb)^2)
+ *   Eq. (4)   U_i = (X_i - mean_i) / sqrt(sum_k (X_i[k] - mean_i)^2)
+ *             (the square in the denominator restored as the variable
+ *             transformation algorithm computes it)
+ *   Eq. (5)   r(X_i, X_j) = U_i . U_j, so all pairs are A A^T with A = U,
+ *             of which only the upper triangle is needed.
+ *   Eq. (9)-(19)  direct bijective mapping between a job id and its
+ *             upper-triangle cell, applied to t x t tiles (Sec. III-C).
+ *
+ * Conventions common to every entry point:
+ *   - Calls are asynchronous on `stream`; results are valid after the
+ *     stream has been synchronised.
+ *   - Every argument error is detected on the host before anything is
+ *     launched and returned as a pcc_status; nothing is launched then.
+ *   - A HIP launch error is returned as PCC_E_HIP.  No C++ exception crosses
+ *     this interface.
+ *   - Calls on distinct streams are thread-safe.  Calls that share an output
+ *     buffer race.
+ *   - Degenerate profiles (zero sum of squared deviations, or a NaN/Inf
+ *     sample) give r = NaN for every pair they are in.
+ */
+#ifndef PCC_H
+#define PCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PCC_OK = 0,
+  PCC_E_ARG = -1,        /* null pointer or bad scalar argument */
+  PCC_E_SHAPE = -2,      /* n, l, ld or a size out of the supported range */
+  PCC_E_MODE = -3,       /* unknown or unsupported precision mode */
+  PCC_E_CAPACITY = -4,   /* reported by pcc_edges_status: edge list overflow */
+  PCC_E_HIP = -5,        /* a HIP runtime call failed */
+  PCC_E_WORKSPACE = -6,  /* workspace missing or too small */
+  PCC_E_DEVICE = -7      /* no usable gfx950 device */
+} pcc_status;
+
+/* Element type of the input matrix X. */
+typedef enum { PCC_IN_F32 = 0, PCC_IN_F64 = 1 } pcc_in_t;
+
+/* Arithmetic of the tile contraction (all accumulate in FP32 on MFMA):
+ *   PCC_FP32          z in FP32, v_mfma_f32_32x32x2_f32.
+ *   PCC_SPLIT_BF16X3  z = hi + lo with hi = bf16(z), lo = bf16(z - hi);
+ *                     r = hi.hi + hi.lo + lo.hi, v_mfma_f32_32x32x16_bf16.
+ *   PCC_BF16          z in BF16.
+ *   PCC_FP16          z*sqrt(l) in FP16 (unit RMS entries), r = acc / l. */
+typedef enum {
+  PCC_FP32 = 0,
+  PCC_SPLIT_BF16X3 = 1,
+  PCC_BF16 = 2,
+  PCC_FP16 = 3
+} pcc_mode_t;
+
+/* Layout of the transformed matrix Z in device memory (written by
+ * pcc_normalize, read by every other entry point).  Z is n_pad rows of
+ * row_bytes bytes.  A row is a sequence of 128-byte chunks, each holding
+ * kchunk consecutive samples:
+ *   FP32:  32 floats;             BF16 / FP16: 64 halves;
+ *   SPLIT: 32 bf16 hi values followed by the 32 matching bf16 lo values.
+ * Samples l..l_pad-1 and rows n..n_pad-1 are zero.  n_pad is a multiple of
+ * 256 and l_pad a multiple of kchunk. */
+typedef struct {
+  int64_t n, l;          /* profiles and samples per profile */
+  int64_t n_pad, l_pad;  /* padded sizes */
+  int64_t row_bytes;     /* bytes of one Z row (l_pad / kchunk * 128) */
+  int64_t bytes;         /* n_pad * row_bytes */
+  int32_t mode;          /* pcc_mode_t */
+  int32_t kchunk;        /* samples per 128-byte chunk */
+} pcc_zdesc;
+
+/* Tile schedule of the all-pairs kernels.
+ *   tile:  256 or 128, the side t of one tile job (Sec. III-C).
+ *   order: 0 = tile ids in the paper's order (row by row, Eq. (16)-(19));
+ *          1 = banded order: the tile triangle is cut into bands of `band`
+ *              tile rows; a band is walked column by column, so consecutive
+ *              ids share row and column panels.  Both are bijections.
+ *   grid:  persistent workgroups, 0 = one per compute unit times occupancy.
+ * Identical results for every schedule (no split-K, no atomics on r). */
+typedef struct {
+  int32_t tile;
+  int32_t order;
+  int32_t band;
+  int32_t grid;
+} pcc_tile_cfg;
+
+/* Human-readable name of a status code (static string). */
+const char *pcc_status_string(pcc_status s);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t pcc_version(void);
+
+/* Fill *out with the Z layout for n profiles of l samples in `mode`.
+ * Host only, pure.  Requires 2 <= n <= 2^31-1 and 2 <= l <= 2^24. */
+pcc_status pcc_z_layout(int64_t n, int64_t l, pcc_mode_t mode, pcc_zdesc *out);
+
+/* Default tile schedule for a layout (host only, pure). */
+pcc_status pcc_default_cfg(const pcc_zdesc *zd, pcc_tile_cfg *out);
+
+/* Variable transformation, Eq. (4) (a1 of the hot path).
+ *   x      device, n rows of l samples, row pitch ldx elements (ldx >= l),
+ *          element type xt.
+ *   z      device, zd->bytes bytes, written in the layout of *zd, padding
+ *          included.  Must not overlap x.
+ *   stats  device, nullable: 2*n doubles, stats[2i] = mean of row i,
+ *          stats[2i+1] = sum of squared deviations M2 (both FP64).
+ *   n_degenerate  device int32, nullable: set to the number of rows with
+ *          M2 == 0 or a non-finite M2; those rows of z are NaN.
+ * Statistics are FP64 (two passes over the row, mean then M2); z is
+ * (x - mean) / sqrt(M2) in FP64, then rounded to the mode's format. */
+pcc_status pcc_normalize(const void *x, pcc_in_t xt, int64_t ldx,
+                         const pcc_zdesc *zd, void *z, double *stats,
+                         int32_t *n_degenerate, void *stream);
+
+/* Bytes of device workspace an operation needs (0 = none; the workspace
+ * pointer may then be NULL).  op: 0 allpairs, 1 edges, 2 permtest. */
+size_t pcc_workspace_size(const pcc_zdesc *zd, int32_t op);
+
+/* All pairs (a2-a5 of the hot path): tile jobs placed by the bijection of
+ * Eq. (16)-(19), each tile of Z Z^T contracted on MFMA, and
+ *   r[J'] = clamp(Z_y . Z_x, -1, 1)   for every 0 <= y < x < n,
+ * with J' = F_{n-1}(y) + (x - 1) - y the strict-upper-triangle index (the
+ * diagonal-free adaptation of Eq. (9)-(10)): row y of the triangle is
+ * contiguous.  r: device, n(n-1)/2 floats.  cfg may be NULL (default). */
+pcc_status pcc_allpairs(const pcc_zdesc *zd, const void *z, float *r,
+                        const pcc_tile_cfg *cfg, void *workspace, void *stream);
+
+/* Thresholded edge list (a4 (ii)): every pair y < x with |r| >= thr (r
+ * clamped as above; NaN never qualifies) is appended as ij[2s] = y,
+ * ij[2s+1] = x, rv[s] = r for a slot s < cap.  *count (device int64) is
+ * zeroed by the call and receives the true number of such pairs, which may
+ * exceed cap (then only cap are stored: call again with a larger list).
+ * The list is unordered.  ij, rv: device; cap >= 0. */
+pcc_status pcc_threshold_edges(const pcc_zdesc *zd, const void *z, float thr,
+                               int32_t *ij, float *rv, int64_t cap,
+                               int64_t *count, const pcc_tile_cfg *cfg,
+                               void *workspace, void *stream);
+
+/* Host helper after pcc_threshold_edges has completed: PCC_OK if
+ * count <= cap, PCC_E_CAPACITY otherwise (count read from host memory). */
+pcc_status pcc_edges_status(int64_t count_host, int64_t cap);
+
+/* Permutation test (a6), one persistent launch for all P permutations.
+ * For every pair y < x:
+ *   r_obs = Z_y . Z_x,  r_p = sum_k Z_y[k] Z_x[perm_p[k]],
+ *   counts[J'] = #{p : |r_p| >= |r_obs|}  (ties counted; -1 if r_obs is NaN)
+ * The second operand (column x) is permuted; Z's mean and norm are
+ * invariant under a permutation, so Z is not renormalised.
+ *   perms  device int32, P rows of l entries, each a permutation of 0..l-1
+ *          (entries are not validated on the device; values outside
+ *          [0, l) read zero padding or neighbouring samples).
+ *   counts device int32, n(n-1)/2.
+ * Supported: mode FP32 or SPLIT_BF16X3, l_pad <= pcc_permtest_max_l(). */
+pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
+                        const int32_t *perms, int32_t P, int32_t *counts,
+                        void *workspace, void *stream);
+
+/* Largest l_pad pcc_permtest accepts (its column panel stays in LDS). */
+int64_t pcc_permtest_max_l(pcc_mode_t mode);
+
+/* ---- Uneven batches (a7) ----------------------------------------------
+ * One item per dataset.  The plan uploads a descriptor table into the
+ * caller's workspace and records, into one hipGraph, the batched
+ * normalisation (all datasets) and one persistent all-pairs kernel whose
+ * workgroups draw tile jobs from a device counter over the concatenated
+ * job space (dynamic distribution with a shared integer counter, Sec.
+ * III-B).  Launching the plan replays the graph on a stream. */
+typedef struct {
+  const void *x;      /* device input, n x l, pitch ldx, type xt */
+  int64_t ldx;
+  int64_t n, l;
+  int32_t xt;         /* pcc_in_t */
+  int32_t tile;       /* 256 or 128, 0 = library default for (n, l) */
+  void *z;            /* device, pcc_z_layout(n, l, mode).bytes bytes */
+  float *r;           /* device, n(n-1)/2 floats */
+} pcc_batch_item;
+
+typedef struct pcc_batch_plan pcc_batch_plan;
+
+/* Workspace bytes a batch of D items needs. */
+size_t pcc_batch_workspace_size(int32_t D);
+
+/* Build a plan (host work + one synchronous upload of the descriptor table
+ * on `stream`).  Items must stay valid for the plan's life; all items use
+ * `mode`. */
+pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items,
+                                 pcc_mode_t mode, void *workspace,
+                                 size_t workspace_bytes, void *stream,
+                                 pcc_batch_plan **plan);
+/* Replay the plan's graph on `stream` (asynchronous). */
+pcc_status pcc_batch_plan_launch(pcc_batch_plan *plan, void *stream);
+/* Total tile jobs of the plan (for accounting). */
+int64_t pcc_batch_plan_jobs(const pcc_batch_plan *plan);
+pcc_status pcc_batch_plan_destroy(pcc_batch_plan *plan);
+
+/* ---- Job maps (a2), host side, for tests and tooling -------------------
+ * Inclusive map over an m x m triangle (diagonal counted in), Eq. (9)-(15):
+ * J = F_m(y) + x - y with F_m(y) = y(2m - y + 1)/2; inverse by Eq. (14)-(15)
+ * evaluated in FP64, then corrected in int64 so that F_m(y) <= J < F_m(y+1)
+ * holds exactly. */
+int64_t pcc_job_of_cell(int64_t m, int64_t y, int64_t x);
+void pcc_cell_of_job(int64_t m, int64_t J, int64_t *y, int64_t *x);
+/* Exclusive (strict upper) map over n profiles: J' = F_{n-1}(y) + x-1-y. */
+int64_t pcc_packed_index(int64_t n, int64_t y, int64_t x);
+void pcc_packed_cell(int64_t n, int64_t Jp, int64_t *y, int64_t *x);
+/* Vector forms: cells of `count` ids starting at J0 (host arrays).
+ * diag != 0: inclusive map over m; diag == 0: exclusive map over m. */
+pcc_status pcc_cells_host(int64_t m, int32_t diag, int64_t J0, int64_t count,
+                          int64_t *y, int64_t *x);
+/* Tile order of a schedule: the tile cell of `count` consecutive job ids
+ * starting at J0 under cfg->order/cfg->band over an m x m tile triangle. */
+pcc_status pcc_tile_order_host(int64_t m, const pcc_tile_cfg *cfg, int64_t J0,
+                               int64_t count, int64_t *yt, int64_t *xt);
+/* Device form of pcc_cells_host, computed by the same device code the tile
+ * kernels use; y and x are device arrays of `count` entries. */
+pcc_status pcc_cells_device(int64_t m, int32_t diag, int64_t J0, int64_t count,
+                            int64_t *y, int64_t *x, void *stream);
+
+/* ---- Autotuning ---------------------------------------------------------
+ * Time each candidate schedule of pcc_allpairs on the caller's z (r is
+ * overwritten) with hipEvents and return the fastest in *best.  `cands`
+ * may be NULL (built-in candidate list); times_ms (host, nullable) gets
+ * the median time of every candidate. */
+pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r,
+                        const pcc_tile_cfg *cands, int32_t ncands,
+                        int32_t reps, pcc_tile_cfg *best, float *times_ms,
+                        void *stream);
+
+/* Number of compute units of the current device (0 if none). */
+int32_t pcc_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCC_H */

@@ -1,0 +1,325 @@
+// Host side of the C ABI declared in include/pcc.h: argument validation,
+// the Z layout, schedule defaults, launches, host job maps and autotuning.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pcc_internal.h"
+
+namespace pcc {
+hipError_t launch_normalize(const void *x, int xt, int64_t ldx, const pcc_zdesc &zd, void *z,
+                            double *stats, int32_t *ndeg, hipStream_t st);
+hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const pcc_tile_cfg &cfg,
+                           int grid, hipStream_t st);
+hipError_t launch_edges(const pcc_zdesc &zd, const void *z, float thr, int32_t *ij, float *rv,
+                        int64_t cap, int64_t *count, const pcc_tile_cfg &cfg, int grid,
+                        hipStream_t st);
+hipError_t launch_cells(int64_t m, int diag, int64_t J0, int64_t count, int64_t *y, int64_t *x,
+                        hipStream_t st);
+int tile_occupancy(int mode, int tile, int epi);
+hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *perms, int32_t P,
+                           int32_t *counts, int cus, hipStream_t st);
+int64_t permtest_max_l(int mode);
+
+namespace {
+
+constexpr int64_t kMaxN = 2147483647LL;  // (i, j) of an edge are int32
+constexpr int64_t kMaxL = 1LL << 24;
+
+bool valid_mode(int m) { return m >= PCC_FP32 && m <= PCC_FP16; }
+
+pcc_status check_zdesc(const pcc_zdesc *zd) {
+  if (!zd) return PCC_E_ARG;
+  if (!valid_mode(zd->mode)) return PCC_E_MODE;
+  pcc_zdesc ref;
+  const pcc_status s = pcc_z_layout(zd->n, zd->l, (pcc_mode_t)zd->mode, &ref);
+  if (s != PCC_OK) return s;
+  if (ref.n_pad != zd->n_pad || ref.l_pad != zd->l_pad || ref.row_bytes != zd->row_bytes ||
+      ref.bytes != zd->bytes || ref.kchunk != zd->kchunk)
+    return PCC_E_SHAPE;
+  return PCC_OK;
+}
+
+pcc_status check_cfg(const pcc_zdesc &zd, const pcc_tile_cfg *in, pcc_tile_cfg &out) {
+  if (in) {
+    out = *in;
+  } else {
+    pcc_default_cfg(&zd, &out);
+  }
+  if (out.tile != 128 && out.tile != 256) return PCC_E_ARG;
+  if (out.order != 0 && out.order != 1) return PCC_E_ARG;
+  if (out.order == 1 && out.band < 1) return PCC_E_ARG;
+  if (out.grid < 0) return PCC_E_ARG;
+  return PCC_OK;
+}
+
+int device_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return cus;
+}
+
+int grid_for(const pcc_zdesc &zd, const pcc_tile_cfg &cfg, int epi) {
+  const int64_t m = (zd.n + cfg.tile - 1) / cfg.tile;
+  const int64_t jobs = m * (m + 1) / 2;
+  int64_t g = cfg.grid;
+  if (g == 0) {
+    const int cus = device_cus();
+    int occ = tile_occupancy(zd.mode, cfg.tile, epi);
+    if (occ < 1) occ = 1;
+    g = (int64_t)(cus > 0 ? cus : 256) * occ;
+  }
+  if (g > jobs) g = jobs;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+pcc_status hip_status(hipError_t e) { return e == hipSuccess ? PCC_OK : PCC_E_HIP; }
+
+}  // namespace
+}  // namespace pcc
+
+using namespace pcc;
+
+extern "C" {
+
+const char *pcc_status_string(pcc_status s) {
+  switch (s) {
+    case PCC_OK: return "PCC_OK";
+    case PCC_E_ARG: return "PCC_E_ARG: null pointer or invalid argument";
+    case PCC_E_SHAPE: return "PCC_E_SHAPE: size outside the supported range";
+    case PCC_E_MODE: return "PCC_E_MODE: unknown or unsupported precision mode";
+    case PCC_E_CAPACITY: return "PCC_E_CAPACITY: edge list capacity exceeded";
+    case PCC_E_HIP: return "PCC_E_HIP: HIP runtime error";
+    case PCC_E_WORKSPACE: return "PCC_E_WORKSPACE: workspace missing or too small";
+    case PCC_E_DEVICE: return "PCC_E_DEVICE: no usable device";
+  }
+  return "unknown pcc_status";
+}
+
+int32_t pcc_version(void) { return 10000; }
+
+pcc_status pcc_z_layout(int64_t n, int64_t l, pcc_mode_t mode, pcc_zdesc *out) {
+  if (!out) return PCC_E_ARG;
+  if (!valid_mode(mode)) return PCC_E_MODE;
+  if (n < 2 || n > kMaxN || l < 2 || l > kMaxL) return PCC_E_SHAPE;
+  pcc_zdesc d;
+  memset(&d, 0, sizeof(d));
+  d.n = n;
+  d.l = l;
+  d.mode = mode;
+  d.kchunk = kchunk_of(mode);
+  d.n_pad = (n + kRowPadMultiple - 1) / kRowPadMultiple * kRowPadMultiple;
+  d.l_pad = (l + d.kchunk - 1) / d.kchunk * d.kchunk;
+  d.row_bytes = d.l_pad / d.kchunk * kChunkBytes;
+  d.bytes = d.n_pad * d.row_bytes;
+  *out = d;
+  return PCC_OK;
+}
+
+pcc_status pcc_default_cfg(const pcc_zdesc *zd, pcc_tile_cfg *out) {
+  if (!zd || !out) return PCC_E_ARG;
+  pcc_tile_cfg c;
+  // Large triangles: 256-wide tiles (twice the arithmetic per staged byte)
+  // in the banded order.  Small ones: 128-wide tiles so that every compute
+  // unit gets work.
+  const int64_t m256 = (zd->n + 255) / 256;
+  if (m256 * (m256 + 1) / 2 >= 4 * 256) {
+    c.tile = 256;
+    c.order = 1;
+    c.band = 8;
+  } else {
+    c.tile = 128;
+    c.order = 1;
+    c.band = 4;
+  }
+  c.grid = 0;
+  *out = c;
+  return PCC_OK;
+}
+
+pcc_status pcc_normalize(const void *x, pcc_in_t xt, int64_t ldx, const pcc_zdesc *zd, void *z,
+                         double *stats, int32_t *n_degenerate, void *stream) {
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (!x || !z) return PCC_E_ARG;
+  if (xt != PCC_IN_F32 && xt != PCC_IN_F64) return PCC_E_ARG;
+  if (ldx < zd->l) return PCC_E_SHAPE;
+  return hip_status(launch_normalize(x, xt, ldx, *zd, z, stats, n_degenerate, (hipStream_t)stream));
+}
+
+size_t pcc_workspace_size(const pcc_zdesc *zd, int32_t op) {
+  (void)zd;
+  (void)op;
+  return 0;
+}
+
+pcc_status pcc_allpairs(const pcc_zdesc *zd, const void *z, float *r, const pcc_tile_cfg *cfg,
+                        void *workspace, void *stream) {
+  (void)workspace;
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (!z || !r) return PCC_E_ARG;
+  pcc_tile_cfg c;
+  s = check_cfg(*zd, cfg, c);
+  if (s != PCC_OK) return s;
+  return hip_status(launch_allpairs(*zd, z, r, c, grid_for(*zd, c, 0), (hipStream_t)stream));
+}
+
+pcc_status pcc_threshold_edges(const pcc_zdesc *zd, const void *z, float thr, int32_t *ij,
+                               float *rv, int64_t cap, int64_t *count, const pcc_tile_cfg *cfg,
+                               void *workspace, void *stream) {
+  (void)workspace;
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (!z || !count || cap < 0 || (cap > 0 && (!ij || !rv))) return PCC_E_ARG;
+  if (!(thr == thr)) return PCC_E_ARG;  // NaN threshold
+  pcc_tile_cfg c;
+  s = check_cfg(*zd, cfg, c);
+  if (s != PCC_OK) return s;
+  return hip_status(
+      launch_edges(*zd, z, thr, ij, rv, cap, count, c, grid_for(*zd, c, 1), (hipStream_t)stream));
+}
+
+pcc_status pcc_edges_status(int64_t count_host, int64_t cap) {
+  if (count_host < 0 || cap < 0) return PCC_E_ARG;
+  return count_host > cap ? PCC_E_CAPACITY : PCC_OK;
+}
+
+int64_t pcc_permtest_max_l(pcc_mode_t mode) { return permtest_max_l(mode); }
+
+pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z, const int32_t *perms, int32_t P,
+                        int32_t *counts, void *workspace, void *stream) {
+  (void)workspace;
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (!z || !counts || P < 0 || (P > 0 && !perms)) return PCC_E_ARG;
+  if (permtest_max_l(zd->mode) <= 0) return PCC_E_MODE;
+  if (zd->l_pad > permtest_max_l(zd->mode)) return PCC_E_SHAPE;
+  const int cus = device_cus();
+  return hip_status(
+      launch_permtest(*zd, z, perms, P, counts, cus > 0 ? cus : 256, (hipStream_t)stream));
+}
+
+int64_t pcc_job_of_cell(int64_t m, int64_t y, int64_t x) { return tri_F(m, y) + x - y; }
+
+void pcc_cell_of_job(int64_t m, int64_t J, int64_t *y, int64_t *x) {
+  const Cell c = tri_cell(m, J);
+  if (y) *y = c.y;
+  if (x) *x = c.x;
+}
+
+int64_t pcc_packed_index(int64_t n, int64_t y, int64_t x) { return packed_index(n, y, x); }
+
+void pcc_packed_cell(int64_t n, int64_t Jp, int64_t *y, int64_t *x) {
+  const Cell c = packed_cell(n, Jp);
+  if (y) *y = c.y;
+  if (x) *x = c.x;
+}
+
+pcc_status pcc_cells_host(int64_t m, int32_t diag, int64_t J0, int64_t count, int64_t *y,
+                          int64_t *x) {
+  if (count < 0 || (count > 0 && (!y || !x)) || m < 1 || J0 < 0) return PCC_E_ARG;
+  const int64_t total = diag ? m * (m + 1) / 2 : m * (m - 1) / 2;
+  if (J0 + count > total) return PCC_E_SHAPE;
+  for (int64_t t = 0; t < count; ++t) {
+    const Cell c = diag ? tri_cell(m, J0 + t) : packed_cell(m, J0 + t);
+    y[t] = c.y;
+    x[t] = c.x;
+  }
+  return PCC_OK;
+}
+
+pcc_status pcc_tile_order_host(int64_t m, const pcc_tile_cfg *cfg, int64_t J0, int64_t count,
+                               int64_t *yt, int64_t *xt) {
+  if (!cfg || count < 0 || (count > 0 && (!yt || !xt)) || m < 1 || J0 < 0) return PCC_E_ARG;
+  if (cfg->order != 0 && cfg->order != 1) return PCC_E_ARG;
+  if (cfg->order == 1 && cfg->band < 1) return PCC_E_ARG;
+  if (J0 + count > m * (m + 1) / 2) return PCC_E_SHAPE;
+  for (int64_t t = 0; t < count; ++t) {
+    const Cell c = tile_of_job(m, cfg->order, cfg->band, J0 + t);
+    yt[t] = c.y;
+    xt[t] = c.x;
+  }
+  return PCC_OK;
+}
+
+pcc_status pcc_cells_device(int64_t m, int32_t diag, int64_t J0, int64_t count, int64_t *y,
+                            int64_t *x, void *stream) {
+  if (count < 0 || (count > 0 && (!y || !x)) || m < 1 || J0 < 0) return PCC_E_ARG;
+  const int64_t total = diag ? m * (m + 1) / 2 : m * (m - 1) / 2;
+  if (J0 + count > total) return PCC_E_SHAPE;
+  return hip_status(launch_cells(m, diag ? 1 : 0, J0, count, y, x, (hipStream_t)stream));
+}
+
+int32_t pcc_device_cus(void) { return device_cus(); }
+
+pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_tile_cfg *cands,
+                        int32_t ncands, int32_t reps, pcc_tile_cfg *best, float *times_ms,
+                        void *stream) {
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (!z || !r || !best || reps < 1 || ncands < 0 || (ncands > 0 && !cands)) return PCC_E_ARG;
+  std::vector<pcc_tile_cfg> list;
+  if (ncands > 0) {
+    list.assign(cands, cands + ncands);
+  } else {
+    const int bands[] = {1, 2, 4, 8, 16};
+    for (int tile : {256, 128}) {
+      list.push_back(pcc_tile_cfg{tile, 0, 1, 0});
+      for (int b : bands)
+        if (b > 1) list.push_back(pcc_tile_cfg{tile, 1, b, 0});
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return PCC_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return PCC_E_HIP;
+  }
+  float best_t = INFINITY;
+  int best_i = -1;
+  pcc_status rs = PCC_OK;
+  for (size_t k = 0; k < list.size() && rs == PCC_OK; ++k) {
+    pcc_tile_cfg c;
+    if (check_cfg(*zd, &list[k], c) != PCC_OK) {
+      if (times_ms) times_ms[k] = INFINITY;
+      continue;
+    }
+    const int grid = grid_for(*zd, c, 0);
+    std::vector<float> ts;
+    for (int rep = 0; rep <= reps && rs == PCC_OK; ++rep) {  // rep 0 warms up
+      if (hipEventRecord(e0, st) != hipSuccess || launch_allpairs(*zd, z, r, c, grid, st) != hipSuccess ||
+          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rs = PCC_E_HIP;
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) ts.push_back(ms);
+    }
+    if (rs != PCC_OK) break;
+    std::sort(ts.begin(), ts.end());
+    const float med = ts[ts.size() / 2];
+    if (times_ms) times_ms[k] = med;
+    if (med < best_t) {
+      best_t = med;
+      best_i = (int)k;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rs != PCC_OK) return rs;
+  if (best_i < 0) return PCC_E_ARG;
+  *best = list[best_i];
+  return PCC_OK;
+}
+
+}  // extern "C"

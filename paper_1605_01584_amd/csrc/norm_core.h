@@ -1,0 +1,193 @@
+// Device core of the variable transformation, Eq. (4), shared by the
+// single-matrix kernel (normalize.hip) and the uneven-batch kernel
+// (batched.hip).
+//
+// One 64-lane wave owns one row.  The row is read once from HBM with
+// coalesced 16-byte loads, kept in registers in its input type (units of 4
+// or 8 consecutive samples per lane, up to kCache units per lane; longer rows
+// are re-read, from L2, by the later passes), and reduced across the wave in
+// FP64:
+//   pass 1  mean = sum x / l
+//   pass 2  M2   = sum (x - mean)^2          (sum of squared deviations, as
+//                                             the transformation algorithm
+//                                             computes it: no division by l)
+//   pass 3  z    = (x - mean) / sqrt(M2)     in FP64, rounded to the mode's
+//                                             format, stored as 16-byte units
+//                                             of the Z layout.
+#pragma once
+
+#include <math.h>
+
+#include "pcc_internal.h"
+
+namespace pcc {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Samples per 16-byte output unit.
+template <int MODE> struct UnitOf { static constexpr int E = (MODE == PCC_FP32) ? 4 : 8; };
+
+// Input samples cached in registers per lane (32: rows up to 2048 samples
+// are read from HBM exactly once).
+template <int MODE> struct CacheOf { static constexpr int C = 32 / UnitOf<MODE>::E; };
+
+template <typename TIn, int E>
+__device__ __forceinline__ void load_unit(const TIn *row, int64_t l, int64_t k0, bool vec,
+                                          TIn (&v)[E]) {
+  if (vec && k0 + E <= l) {
+    if constexpr (sizeof(TIn) == 4) {
+#pragma unroll
+      for (int q = 0; q < E / 4; ++q) {
+        const float4 f = *reinterpret_cast<const float4 *>(row + k0 + 4 * q);
+        v[4 * q + 0] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < E / 2; ++q) {
+        const double2 d = *reinterpret_cast<const double2 *>(row + k0 + 2 * q);
+        v[2 * q + 0] = d.x; v[2 * q + 1] = d.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = (k0 + e < l) ? row[k0 + e] : (TIn)0;
+  }
+}
+
+// Store one unit of E transformed samples (FP64 values) into row `zr`.
+template <int MODE, int E>
+__device__ __forceinline__ void store_unit(unsigned char *zr, int64_t u, const double (&z)[E]) {
+  if constexpr (MODE == PCC_FP32) {
+    float4 o = make_float4((float)z[0], (float)z[1], (float)z[2], (float)z[3]);
+    *reinterpret_cast<float4 *>(zr + u * 16) = o;
+  } else if constexpr (MODE == PCC_BF16) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = (uint32_t)f32_to_bf16_bits((float)z[2 * q]) |
+             ((uint32_t)f32_to_bf16_bits((float)z[2 * q + 1]) << 16);
+    *reinterpret_cast<uint4 *>(zr + u * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if constexpr (MODE == PCC_FP16) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const _Float16 a = (_Float16)(float)z[2 * q];
+      const _Float16 b = (_Float16)(float)z[2 * q + 1];
+      w[q] = (uint32_t)__builtin_bit_cast(uint16_t, a) |
+             ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+    }
+    *reinterpret_cast<uint4 *>(zr + u * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+  } else {  // split: hi = bf16(z), lo = bf16(z - hi), hi and lo halves of a chunk
+    uint32_t wh[4], wl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint16_t h[2], lo[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const double zz = z[2 * q + s];
+        h[s] = f32_to_bf16_bits((float)zz);
+        lo[s] = f32_to_bf16_bits((float)(zz - (double)bf16_bits_to_f32(h[s])));
+      }
+      wh[q] = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+      wl[q] = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
+    }
+    const int64_t c = u >> 2, part = u & 3;
+    *reinterpret_cast<uint4 *>(zr + c * 128 + part * 16) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
+    *reinterpret_cast<uint4 *>(zr + c * 128 + 64 + part * 16) =
+        make_uint4(wl[0], wl[1], wl[2], wl[3]);
+  }
+}
+
+// Transform row `row` (< n) of x into row zr of Z.  Called by a whole wave.
+template <typename TIn, int MODE, int kCache>
+__device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_t l, int64_t l_pad,
+                                              unsigned char *__restrict__ zr, double *stats_row,
+                                              int32_t *n_degenerate, double out_scale, bool vec_ok) {
+  constexpr int E = UnitOf<MODE>::E;
+  const int lane = threadIdx.x & 63;
+  const int64_t units = l_pad / E;
+  TIn cache[kCache][E];  // the row stays in registers in its input type
+  // pass 1: sum
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCache; ++c) {
+    const int64_t u = lane + 64 * c;
+    if (u < units) {
+      load_unit<TIn, E>(xr, l, u * E, vec_ok, cache[c]);
+#pragma unroll
+      for (int e = 0; e < E; ++e) s += (double)cache[c][e];
+    }
+  }
+  for (int64_t u = lane + 64 * kCache; u < units; u += 64) {
+    TIn v[E];
+    load_unit<TIn, E>(xr, l, u * E, vec_ok, v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) s += (double)v[e];
+  }
+  const double mean = wave_sum(s) / (double)l;
+  // pass 2: sum of squared deviations (padding samples excluded)
+  double q = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCache; ++c) {
+    const int64_t u = lane + 64 * c;
+    if (u < units) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double d = (double)cache[c][e] - mean;
+        q += (u * E + e < l) ? d * d : 0.0;
+      }
+    }
+  }
+  for (int64_t u = lane + 64 * kCache; u < units; u += 64) {
+    TIn v[E];
+    load_unit<TIn, E>(xr, l, u * E, vec_ok, v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double d = (double)v[e] - mean;
+      q += (u * E + e < l) ? d * d : 0.0;
+    }
+  }
+  const double m2 = wave_sum(q);
+  const bool degenerate = !(m2 > 0.0) || !(m2 < INFINITY);
+  if (lane == 0) {
+    if (stats_row) {
+      stats_row[0] = mean;
+      stats_row[1] = m2;
+    }
+    if (degenerate && n_degenerate) atomicAdd(n_degenerate, 1);
+  }
+  const double inv = degenerate ? (double)NAN : out_scale / sqrt(m2);
+  // pass 3: transformed samples, zero padding
+#pragma unroll
+  for (int c = 0; c < kCache; ++c) {
+    const int64_t u = lane + 64 * c;
+    if (u < units) {
+      double o[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        o[e] = (u * E + e < l) ? ((double)cache[c][e] - mean) * inv : 0.0;
+      store_unit<MODE, E>(zr, u, o);
+    }
+  }
+  for (int64_t u = lane + 64 * kCache; u < units; u += 64) {
+    TIn v[E];
+    double o[E];
+    load_unit<TIn, E>(xr, l, u * E, vec_ok, v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) o[e] = (u * E + e < l) ? ((double)v[e] - mean) * inv : 0.0;
+    store_unit<MODE, E>(zr, u, o);
+  }
+}
+
+// Zero one padding row of Z (rows n .. n_pad-1).
+__device__ __forceinline__ void zero_row(unsigned char *__restrict__ zr, int64_t row_bytes) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t u = lane; u < row_bytes / 16; u += 64)
+    *reinterpret_cast<uint4 *>(zr + u * 16) = make_uint4(0u, 0u, 0u, 0u);
+}
+
+}  // namespace pcc

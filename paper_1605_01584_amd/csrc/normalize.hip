@@ -1,0 +1,74 @@
+// Variable transformation, Eq. (4), of one matrix: a grid-stride loop of
+// waves over the n_pad rows of Z (padding rows are zeroed).  HBM-bound: it
+// reads n*l input elements and writes n_pad*row_bytes bytes; the FP64
+// arithmetic (about 5 operations per sample) is far below the vector FP64
+// rate.
+#include "norm_core.h"
+
+namespace pcc {
+namespace {
+
+constexpr int kWaves = 4;  // waves (rows) per workgroup
+
+template <typename TIn, int MODE>
+__global__ __launch_bounds__(64 * kWaves) void normalize_kernel(
+    const TIn *__restrict__ x, int64_t ldx, int64_t n, int64_t l, int64_t n_pad, int64_t l_pad,
+    int64_t row_bytes, unsigned char *__restrict__ z, double *__restrict__ stats,
+    int32_t *__restrict__ n_degenerate, double out_scale, int vec_ok) {
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  for (int64_t row = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); row < n_pad;
+       row += stride) {
+    unsigned char *zr = z + row * row_bytes;
+    if (row >= n) {
+      zero_row(zr, row_bytes);
+      continue;
+    }
+    normalize_row<TIn, MODE, CacheOf<MODE>::C>(x + row * ldx, l, l_pad, zr,
+                                              stats ? stats + 2 * row : nullptr, n_degenerate,
+                                              out_scale, vec_ok != 0);
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int32_t v) { *p = v; }
+
+template <typename TIn, int MODE>
+hipError_t launch_norm(const TIn *x, int64_t ldx, const pcc_zdesc &zd, void *z, double *stats,
+                       int32_t *ndeg, hipStream_t st) {
+  const bool vec = ((ldx * (int64_t)sizeof(TIn)) % 16 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
+  const double out_scale = (MODE == PCC_FP16) ? sqrt((double)zd.l) : 1.0;
+  int64_t blocks = (zd.n_pad + kWaves - 1) / kWaves;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL((normalize_kernel<TIn, MODE>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
+                     st, x, ldx, zd.n, zd.l, zd.n_pad, zd.l_pad, zd.row_bytes, (unsigned char *)z,
+                     stats, ndeg, out_scale, vec ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename TIn>
+hipError_t dispatch_mode(const TIn *x, int64_t ldx, const pcc_zdesc &zd, void *z, double *stats,
+                         int32_t *ndeg, hipStream_t st) {
+  switch (zd.mode) {
+    case PCC_FP32: return launch_norm<TIn, PCC_FP32>(x, ldx, zd, z, stats, ndeg, st);
+    case PCC_SPLIT_BF16X3: return launch_norm<TIn, PCC_SPLIT_BF16X3>(x, ldx, zd, z, stats, ndeg, st);
+    case PCC_BF16: return launch_norm<TIn, PCC_BF16>(x, ldx, zd, z, stats, ndeg, st);
+    case PCC_FP16: return launch_norm<TIn, PCC_FP16>(x, ldx, zd, z, stats, ndeg, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_normalize(const void *x, int xt, int64_t ldx, const pcc_zdesc &zd, void *z,
+                            double *stats, int32_t *ndeg, hipStream_t st) {
+  if (ndeg) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(1), 0, st, ndeg, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (xt == PCC_IN_F64)
+    return dispatch_mode<double>((const double *)x, ldx, zd, z, stats, ndeg, st);
+  return dispatch_mode<float>((const float *)x, ldx, zd, z, stats, ndeg, st);
+}
+
+}  // namespace pcc

@@ -1,0 +1,125 @@
+// Internal definitions shared by the HIP sources of libpcc (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pcc.h"
+
+#define PCC_HD __host__ __device__ __forceinline__
+
+namespace pcc {
+
+// ---------------------------------------------------------------------------
+// Job maps (Sec. III-B/C).  F_m(y) = y(2m - y + 1)/2 counts the cells of the
+// inclusive upper triangle above row y, Eq. (10)/(17).  All integer work is
+// int64: y(2m-y+1) passes INT32_MAX already for m around 46341.
+
+PCC_HD int64_t tri_F(int64_t m, int64_t y) { return (y * (2 * m - y + 1)) >> 1; }
+
+struct Cell {
+  int64_t y, x;
+};
+
+// Inverse of J = F_m(y) + x - y, Eq. (14)-(15)/(18)-(19).  The ceiling of
+// Eq. (14) is evaluated in FP64; the guess is then corrected in int64 until
+// F_m(y) <= J < F_m(y+1) holds, so the result is exact for every m < 2^31
+// whatever the rounding of sqrt (a 1-ulp-low sqrt would otherwise move the
+// last id of every row to the next row).
+PCC_HD Cell tri_cell(int64_t m, int64_t J) {
+  const double dm = (double)m;
+  double t = dm * dm + dm + 0.25 - 2.0 * ((double)J + 1.0);
+  t = t > 0.0 ? t : 0.0;
+  int64_t g = (int64_t)ceil(dm - 0.5 - sqrt(t));
+  g = g < 0 ? 0 : (g > m - 1 ? m - 1 : g);
+  while (g + 1 < m && tri_F(m, g + 1) <= J) ++g;
+  while (g > 0 && tri_F(m, g) > J) --g;
+  return Cell{g, J + g - tri_F(m, g)};
+}
+
+// Strict upper triangle over n profiles: cells y < x < n are the inclusive
+// triangle over n - 1 with x shifted by one (the diagonal-free adaptation the
+// framework allows).  J' = F_{n-1}(y) + (x - 1) - y.
+PCC_HD int64_t packed_index(int64_t n, int64_t y, int64_t x) {
+  return tri_F(n - 1, y) + (x - 1) - y;
+}
+PCC_HD Cell packed_cell(int64_t n, int64_t Jp) {
+  const Cell c = tri_cell(n - 1, Jp);
+  return Cell{c.y, c.x + 1};
+}
+
+// Column of offset o in a small triangle walked column by column (column c
+// holds c + 1 cells): the largest c with c(c+1)/2 <= o.
+PCC_HD int64_t small_tri_col(int64_t o) {
+  int64_t c = (int64_t)((sqrt(8.0 * (double)o + 1.0) - 1.0) * 0.5);
+  if (c < 0) c = 0;
+  while ((c + 1) * (c + 2) / 2 <= o) ++c;
+  while (c > 0 && c * (c + 1) / 2 > o) --c;
+  return c;
+}
+
+// Banded tile order: the m x m tile triangle is cut into bands of H tile
+// rows; band b covers rows [bH, bH + h), h = min(H, m - bH), and is walked
+// column by column, top to bottom inside a column.  The jobs before band b
+// are exactly the cells of the rows above it, F_m(bH), so the band of id J is
+// the row-major row of J (Eq. (18)) divided by H.  A bijection from
+// [0, m(m+1)/2) onto the inclusive tile triangle.
+PCC_HD Cell band_cell(int64_t m, int64_t H, int64_t J) {
+  const Cell rm = tri_cell(m, J);
+  const int64_t r0 = (rm.y / H) * H;
+  const int64_t h = (m - r0) < H ? (m - r0) : H;
+  const int64_t o = J - tri_F(m, r0);
+  const int64_t T = h * (h + 1) / 2;
+  if (o < T) {
+    const int64_t c = small_tri_col(o);
+    return Cell{r0 + (o - c * (c + 1) / 2), r0 + c};
+  }
+  const int64_t q = o - T;
+  return Cell{r0 + q % h, r0 + h + q / h};
+}
+
+PCC_HD Cell tile_of_job(int64_t m, int order, int64_t H, int64_t J) {
+  return (order == 1 && H > 1) ? band_cell(m, H, J) : tri_cell(m, J);
+}
+
+// ---------------------------------------------------------------------------
+// Number formats.
+
+// float -> bf16 bits, round to nearest even; NaN stays a quiet NaN.
+PCC_HD uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+PCC_HD float bf16_bits_to_f32(uint16_t h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+// Layout constants.
+constexpr int kChunkBytes = 128;
+constexpr int kRowPadMultiple = 256;
+
+inline int kchunk_of(int mode) { return (mode == PCC_FP32 || mode == PCC_SPLIT_BF16X3) ? 32 : 64; }
+
+// Kernel launch parameters of the tile kernels.
+struct TileArgs {
+  const unsigned char *z;  // Z base
+  int64_t row_bytes;
+  int64_t n;               // profiles
+  int64_t m;               // tiles per side
+  int64_t njobs;           // m(m+1)/2
+  int32_t nchunks;         // l_pad / kchunk
+  int32_t order;
+  int32_t band;
+  float scale;             // multiply accumulators by this (FP16: 1/l)
+  // outputs
+  float *r;                // packed triangle (allpairs)
+  float thr;               // edges
+  int32_t *ij;
+  float *rv;
+  int64_t cap;
+  unsigned long long *count;
+};
+
+}  // namespace pcc

@@ -1,0 +1,143 @@
+"""The C-ABI library loads, exports every symbol include/pcc.h declares, and
+rejects bad arguments on the host before launching anything.  CPU only: no
+call here reaches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pcc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    import paper_1605_01584_amd as pcc
+    lib = ctypes.CDLL(pcc.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(pcc.EXPORTED) == names
+
+
+def test_status_strings_and_version():
+    import paper_1605_01584_amd as pcc
+    for s in range(-7, 1):
+        assert pcc.status_string(s).startswith("PCC_")
+    assert pcc.version() >= 10000
+
+
+@pytest.mark.parametrize("mode,kchunk,elem", [("fp32", 32, 4), ("split", 32, 4), ("bf16", 64, 2),
+                                              ("fp16", 64, 2)])
+@pytest.mark.parametrize("n,l", [(2, 2), (2000, 256), (257, 65), (32768, 4096), (65536, 2048)])
+def test_layout(mode, kchunk, elem, n, l):
+    import paper_1605_01584_amd as pcc
+    zd = pcc.z_layout(n, l, mode)
+    assert zd.n == n and zd.l == l and zd.kchunk == kchunk
+    assert zd.n_pad % 256 == 0 and n <= zd.n_pad < n + 256
+    assert zd.l_pad % kchunk == 0 and l <= zd.l_pad < l + kchunk
+    assert zd.row_bytes == zd.l_pad * elem and zd.row_bytes % 128 == 0
+    assert zd.bytes == zd.n_pad * zd.row_bytes
+
+
+def test_layout_rejects():
+    import paper_1605_01584_amd as pcc
+    for n, l in [(1, 10), (0, 10), (10, 1), (10, 0), (2 ** 31, 10), (10, 2 ** 24 + 1)]:
+        with pytest.raises(pcc.PccError) as e:
+            pcc.z_layout(n, l)
+        assert e.value.status == pcc.PCC_E_SHAPE
+    with pytest.raises(pcc.PccError) as e:
+        pcc.z_layout(10, 10, 7)
+    assert e.value.status == pcc.PCC_E_MODE
+
+
+def test_host_argument_errors_return_before_launch():
+    import paper_1605_01584_amd as pcc
+    lib = pcc._lib
+    zd = pcc.z_layout(100, 50, "fp32")
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    # null pointers
+    assert lib.pcc_normalize(None, 0, 50, ctypes.byref(zd), fake, None, None, None) == pcc.PCC_E_ARG
+    assert lib.pcc_normalize(fake, 0, 50, ctypes.byref(zd), None, None, None, None) == pcc.PCC_E_ARG
+    assert lib.pcc_normalize(fake, 0, 50, None, fake, None, None, None) == pcc.PCC_E_ARG
+    assert lib.pcc_allpairs(ctypes.byref(zd), None, fake, None, None, None) == pcc.PCC_E_ARG
+    assert lib.pcc_allpairs(ctypes.byref(zd), fake, None, None, None, None) == pcc.PCC_E_ARG
+    # ld < l, bad input type
+    assert lib.pcc_normalize(fake, 0, 49, ctypes.byref(zd), fake, None, None, None) == pcc.PCC_E_SHAPE
+    assert lib.pcc_normalize(fake, 5, 50, ctypes.byref(zd), fake, None, None, None) == pcc.PCC_E_ARG
+    # inconsistent descriptor
+    bad = pcc.z_layout(100, 50, "fp32")
+    bad.row_bytes += 128
+    assert lib.pcc_allpairs(ctypes.byref(bad), fake, fake, None, None, None) == pcc.PCC_E_SHAPE
+    bad = pcc.z_layout(100, 50, "fp32")
+    bad.mode = 9
+    assert lib.pcc_allpairs(ctypes.byref(bad), fake, fake, None, None, None) == pcc.PCC_E_MODE
+    # bad schedules
+    for cfg in [pcc.TileCfg(64, 0, 1, 0), pcc.TileCfg(256, 2, 1, 0), pcc.TileCfg(256, 1, 0, 0),
+                pcc.TileCfg(128, 0, 1, -1)]:
+        assert lib.pcc_allpairs(ctypes.byref(zd), fake, fake, ctypes.byref(cfg), None,
+                                None) == pcc.PCC_E_ARG
+    # edges: null count, negative cap, NaN threshold, cap>0 without arrays
+    assert lib.pcc_threshold_edges(ctypes.byref(zd), fake, 0.5, fake, fake, 10, None, None, None,
+                                   None) == pcc.PCC_E_ARG
+    assert lib.pcc_threshold_edges(ctypes.byref(zd), fake, 0.5, fake, fake, -1, fake, None, None,
+                                   None) == pcc.PCC_E_ARG
+    assert lib.pcc_threshold_edges(ctypes.byref(zd), fake, float("nan"), fake, fake, 10, fake,
+                                   None, None, None) == pcc.PCC_E_ARG
+    assert lib.pcc_threshold_edges(ctypes.byref(zd), fake, 0.5, None, None, 10, fake, None, None,
+                                   None) == pcc.PCC_E_ARG
+    # capacity helper
+    assert lib.pcc_edges_status(5, 10) == pcc.PCC_OK
+    assert lib.pcc_edges_status(11, 10) == pcc.PCC_E_CAPACITY
+    assert lib.pcc_edges_status(-1, 10) == pcc.PCC_E_ARG
+    # permtest: unsupported mode, too long rows, null perms with P > 0
+    zs = pcc.z_layout(100, 50, "bf16")
+    assert lib.pcc_permtest(ctypes.byref(zs), fake, fake, 3, fake, None, None) == pcc.PCC_E_MODE
+    zl = pcc.z_layout(100, 100000, "fp32")
+    assert lib.pcc_permtest(ctypes.byref(zl), fake, fake, 3, fake, None, None) == pcc.PCC_E_SHAPE
+    assert lib.pcc_permtest(ctypes.byref(zd), fake, None, 3, fake, None, None) == pcc.PCC_E_ARG
+    assert lib.pcc_permtest(ctypes.byref(zd), fake, fake, -1, fake, None, None) == pcc.PCC_E_ARG
+    # batch plan: bad counts / missing workspace
+    plan = ctypes.c_void_p()
+    items = (pcc.BatchItem * 1)()
+    assert lib.pcc_batch_plan_create(0, items, 1, fake, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_ARG
+    assert lib.pcc_batch_plan_create(1, items, 1, None, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_WORKSPACE
+    assert lib.pcc_batch_plan_create(1, items, 1, fake, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_ARG
+    assert lib.pcc_batch_plan_create(1, items, 9, fake, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_MODE
+    assert lib.pcc_batch_plan_launch(None, None) == pcc.PCC_E_ARG
+    assert lib.pcc_batch_plan_destroy(None) == pcc.PCC_E_ARG
+    # maps
+    assert lib.pcc_cells_host(10, 1, 50, 10, fake, fake) == pcc.PCC_E_SHAPE
+    assert lib.pcc_cells_device(10, 1, 0, 5, None, fake, None) == pcc.PCC_E_ARG
+
+
+def test_workspace_sizes():
+    import paper_1605_01584_amd as pcc
+    zd = pcc.z_layout(1000, 100, "split")
+    for op in range(3):
+        assert pcc._lib.pcc_workspace_size(ctypes.byref(zd), op) == 0
+    assert pcc._lib.pcc_batch_workspace_size(64) >= 256 + 64 * 64
+    assert pcc._lib.pcc_batch_workspace_size(64) % 256 == 0
+
+
+def test_default_cfg():
+    import paper_1605_01584_amd as pcc
+    big = pcc.default_cfg(pcc.z_layout(32768, 4096, "split"))
+    assert big.tile == 256 and big.order in (0, 1)
+    small = pcc.default_cfg(pcc.z_layout(600, 100, "split"))
+    assert small.tile == 128
+
+
+def test_permtest_limit_is_lds_bound():
+    import paper_1605_01584_amd as pcc
+    # without a device the library assumes gfx950's 160 KiB per workgroup; with
+    # one it uses the device's limit.  Either way a positive multiple of 32.
+    lim = pcc.permtest_max_l("fp32")
+    assert lim > 0 and lim % 32 == 0
+    assert pcc.permtest_max_l("bf16") == 0

@@ -1,0 +1,108 @@
+"""pcc_normalize (Eq. (4)) on the GPU against the FP64 oracle's
+transformation.  Every call goes through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import decode_z, to_device
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp32", "split", "bf16", "fp16"]
+
+
+def _run(X, mode, dtype=None, stats=True, ld=None):
+    import torch
+    import paper_1605_01584_amd as pcc
+    xt = to_device(X, dtype)
+    if ld is not None and ld != X.shape[1]:
+        big = torch.zeros((X.shape[0], ld), dtype=xt.dtype, device="cuda")
+        big[:, : X.shape[1]] = xt
+        xt = big[:, : X.shape[1]]
+    z, zd, st, nd = pcc.normalize(xt, mode, stats=True, degenerate=True)
+    torch.cuda.synchronize()
+    return z.cpu().numpy(), zd, st.cpu().numpy(), int(nd.item())
+
+
+def _check_values(Z, zd, U, mode):
+    n, l = U.shape
+    dec = decode_z(Z, zd)
+    V = dec["value"]
+    assert np.all(V[n:] == 0.0), "padding rows must be zero"
+    assert np.all(V[:, l:] == 0.0), "padding samples must be zero"
+    A = np.abs(U)
+    d = np.abs(V[:n, :l] - U)
+    if mode == "fp32":
+        assert np.all(d <= 2.0 ** -24 * A + 1e-14)
+    elif mode == "bf16":
+        assert np.all(d <= (2.0 ** -8 + 2.0 ** -24) * A + 1e-14)
+    elif mode == "split":
+        assert np.all(d <= (2.0 ** -16 + 2.0 ** -24) * A + 1e-14)
+        hi = dec["hi"][:n, :l]
+        assert np.all(np.abs(hi - U) <= (2.0 ** -8 + 2.0 ** -24) * A + 1e-14)
+    else:  # fp16 stores z*sqrt(l)
+        S = dec["scaled"][:n, :l]
+        T = U * np.sqrt(l)
+        assert np.all(np.abs(S - T) <= 2.0 ** -11 * np.abs(T) + 3e-8)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config1_fp64_input(mode):
+    X, _ = workloads.config1()
+    U, mean, m2 = oracle.transform(X)
+    Z, zd, st, nd = _run(X, mode)
+    assert nd == 0
+    np.testing.assert_allclose(st[:, 0], mean, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(st[:, 1], m2, rtol=1e-12)
+    _check_values(Z, zd, U, mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("l", [2, 3, 63, 64, 65, 1000, 2049, 4097])
+def test_ragged_lengths_fp32_input(mode, l):
+    rng = np.random.default_rng(l)
+    X = (rng.standard_normal((37, l)) * 3 + 5).astype(np.float32)
+    U, mean, m2 = oracle.transform(X)
+    Z, zd, st, nd = _run(X, mode)
+    assert nd == 0
+    np.testing.assert_allclose(st[:, 0], mean, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(st[:, 1], m2, rtol=1e-12)
+    _check_values(Z, zd, U, mode)
+
+
+@pytest.mark.parametrize("ld", [101, 104, 128])
+def test_row_pitch(ld):
+    # ld = 101 is not a multiple of 4 floats: the scalar load path
+    rng = np.random.default_rng(ld)
+    X = rng.standard_normal((50, 100)).astype(np.float32)
+    U, _, _ = oracle.transform(X)
+    Z, zd, _, _ = _run(X, "fp32", ld=ld)
+    _check_values(Z, zd, U, "fp32")
+
+
+def test_unit_norm_and_zero_sum():
+    rng = np.random.default_rng(1)
+    X = (rng.standard_normal((200, 777)) * 10 + 100).astype(np.float32)
+    Z, zd, _, _ = _run(X, "fp32")
+    V = decode_z(Z, zd)["value"][:200, :777]
+    np.testing.assert_allclose(np.linalg.norm(V, axis=1), 1.0, atol=2e-7)
+    np.testing.assert_allclose(V.sum(axis=1), 0.0, atol=1e-6)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate_rows(mode):
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((10, 40)).astype(np.float32)
+    X[2] = 7.5            # constant
+    X[5, 3] = np.nan      # NaN sample
+    X[8, 0] = np.inf      # Inf sample
+    Z, zd, st, nd = _run(X, mode)
+    assert nd == 3
+    assert st[2, 1] == 0.0
+    V = decode_z(Z, zd)["value"]
+    for r in (2, 5, 8):
+        assert np.all(np.isnan(V[r, :40]))
+        assert np.all(V[r, 40:] == 0.0)
+    for r in (0, 1, 3, 4, 6, 7, 9):
+        assert np.all(np.isfinite(V[r]))
