@@ -1,0 +1,325 @@
+"""Benchmark of the all-pairs Pearson correlation hot path on one MI355X.
+
+Headline workload: n = 32768 profiles x l = 4096 samples (FP32 input, the
+planted-pair N(0,1) distribution), split-BF16 (3-term) tiles.  One step is
+the whole hot path over that matrix: the variable transformation (Eq. (4))
+into the split Z layout, then all upper-triangle tiles placed by the tile-id
+bijection, contracted on MFMA and written as the packed strict-upper r
+triangle.  value = pair-samples/s = n(n-1)/2 * l / step time, inputs
+resident in HBM.
+
+The same JSON line carries the roofline of the dominant kernel (the tile
+kernel, timed with HIP events on the stream it is launched on), the FP32 path
+and the other rows of the path (edges, permutation test, uneven batch) as
+extra objects, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X dense peaks, FLOP/s
+    "bf16": 2.5e15, "fp16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12,
+}
+HBM_PEAK = 8.0e12  # B/s
+MODE_DTYPE = {"split": "bf16", "bf16": "bf16", "fp16": "fp16", "fp32": "fp32"}
+MFMA_PER_MAC = {"split": 3, "bf16": 1, "fp16": 1, "fp32": 1}
+TILE_SOURCES = ["paper_1605_01584_amd/csrc/tile_core.h", "paper_1605_01584_amd/csrc/tiles.hip",
+                "paper_1605_01584_amd/csrc/pcc_internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def tile_source_sha():
+    h = hashlib.sha256()
+    for p in TILE_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def timed(fn, reps, stream):
+    """Median and mean of `reps` runs of fn, HIP events on `stream`."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), float(np.mean(ts))
+
+
+def traffic_from_profile(mode):
+    """HBM bytes per tile-kernel launch from the committed PMC summary, if the
+    tile kernel has not changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"tile_{mode}_n32768_l4096_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("tile_source_sha") != tile_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(X, seconds=10.0):
+    """The FP64 oracle (literal Eq. (1), pair by pair) on seeded 128 x 128
+    check blocks of the same matrix until about `seconds` have passed."""
+    import oracle
+    import workloads
+    n, l = X.shape
+    blocks = workloads.check_blocks(n, nblocks=256, seed=3)
+    done_pairs, t0, used = 0, time.perf_counter(), 0
+    results = []
+    while used < len(blocks) and time.perf_counter() - t0 < seconds:
+        I, J = workloads.block_pairs(n, blocks[used:used + 8])
+        r = oracle.pearson_pairs(X, I, J)
+        results.append((I, J, r))
+        done_pairs += len(I)
+        used += min(8, len(blocks) - used)
+    dt = time.perf_counter() - t0
+    return {
+        "value": done_pairs * l / dt, "unit": "pair-samples/s", "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{used} seeded 128x128 check blocks ({done_pairs} pairs i<j) of the "
+                  f"n={n} l={l} matrix, FP64 literal Eq. (1), {dt:.1f} s",
+    }, results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--l", type=int, default=4096)
+    ap.add_argument("--mode", default="split")
+    ap.add_argument("--no-extras", action="store_true", help="headline step only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the all-pairs path "
+                                   "is measured on a single MI355X (multi-GPU sharding is a "
+                                   "design note, not implemented)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1605_01584_amd as pcc
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n, l, mode = args.n, args.l, args.mode
+    log(f"[bench] generating n={n} l={l} (planted N(0,1), FP32)")
+    X, _ = workloads.config3(n, l)
+    x = torch.from_numpy(X).to(dev)
+    zd = pcc.z_layout(n, l, mode)
+    z = torch.empty(zd.bytes, dtype=torch.uint8, device=dev)
+    npairs = n * (n - 1) // 2
+    r = torch.empty(npairs, dtype=torch.float32, device=dev)
+    cfg = pcc.default_cfg(zd)
+
+    def norm():
+        pcc.normalize(x, mode, z=z)
+
+    def tiles():
+        pcc.allpairs(z, zd, cfg, out=r)
+
+    log(f"[bench] warmup {args.warmup} steps, cfg={cfg}")
+    for _ in range(args.warmup):
+        norm()
+        tiles()
+    torch.cuda.synchronize()
+
+    # Timed region: exactly K steps, synchronised on both sides.  Inside,
+    # HIP events on the launch stream bracket every tile-kernel launch.
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        norm()
+        ev[k][0].record(stream)
+        tiles()
+        ev[k][1].record(stream)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_stop)
+    ms_step = ms_total / args.steps
+    tile_ms = [a.elapsed_time(b) for a, b in ev]
+    tile_avg = float(np.mean(tile_ms))
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, tile kernel {tile_avg:.3f} ms")
+
+    pair_samples = npairs * l
+    value = pair_samples / (ms_step * 1e-3)
+    dt = MODE_DTYPE[mode]
+    alg_flops = 2.0 * pair_samples * MFMA_PER_MAC[mode]
+    achieved = alg_flops / (tile_avg * 1e-3)
+    traffic = traffic_from_profile(mode)
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dt] / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK[dt], "traffic": traffic,
+                "kernel": f"tile_kernel<{mode},{cfg.tile}>",
+                "per_launch": f"{alg_flops:.4e} MFMA flops = 2 x {MFMA_PER_MAC[mode]} x "
+                              f"n(n-1)/2 x l",
+                "useful_frac": (2.0 * pair_samples / (tile_avg * 1e-3)) / PEAK[dt]}
+
+    out = {
+        "metric": "PCC pair-samples/s + MFMA util; split-BF16 vs FP32 path at max|dr|<=1e-5",
+        "value": value, "unit": "pair-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+        "data": "synthetic (seeded N(0,1) with 20 planted pairs, FP32)",
+        "config": {"workload": f"all-pairs PCC n={n} l={l}, split-BF16x3 tiles, "
+                               "normalise + packed upper-triangle r",
+                   "n": n, "l": l, "mode": mode, "tile": cfg.tile, "order": cfg.order,
+                   "band": cfg.band, "parallelism": "1 GPU"},
+        "roofline": roofline,
+    }
+
+    extras = {}
+    if not args.no_extras:
+        # normalisation alone (HBM-bound)
+        nm, _ = timed(norm, 5, stream)
+        nbytes = n * l * 4 + zd.bytes
+        extras["normalize"] = {"ms": nm, "GB_per_s": nbytes / (nm * 1e-3) / 1e9,
+                               "hbm_frac": nbytes / (nm * 1e-3) / HBM_PEAK,
+                               "bytes": nbytes}
+        # FP32 path
+        zd32 = pcc.z_layout(n, l, "fp32")
+        z32 = torch.empty(zd32.bytes, dtype=torch.uint8, device=dev)
+        pcc.normalize(x, "fp32", z=z32)
+        cfg32 = pcc.default_cfg(zd32)
+        t32, _ = timed(lambda: pcc.allpairs(z32, zd32, cfg32, out=r), 3, stream)
+        extras["fp32_path"] = {
+            "tile_ms": t32, "pair_samples_per_s": pair_samples / (t32 * 1e-3),
+            "mfma_frac": 2.0 * pair_samples / (t32 * 1e-3) / PEAK["fp32"],
+            "split_speedup_over_fp32": t32 / tile_avg}
+        # edges epilogue (|r| >= 0.8)
+        cap = 1 << 20
+        ij = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        rv = torch.empty(cap, dtype=torch.float32, device=dev)
+        cnt = torch.empty((), dtype=torch.int64, device=dev)
+        import ctypes
+
+        def edges():
+            pcc._check(pcc._lib.pcc_threshold_edges(
+                ctypes.byref(zd), ctypes.c_void_p(z.data_ptr()), 0.8,
+                ctypes.c_void_p(ij.data_ptr()), ctypes.c_void_p(rv.data_ptr()), cap,
+                ctypes.c_void_p(cnt.data_ptr()), ctypes.byref(cfg), None,
+                ctypes.c_void_p(stream.cuda_stream)), "edges")
+        pcc.normalize(x, mode, z=z)
+        te, _ = timed(edges, 3, stream)
+        extras["edges"] = {"ms": te, "threshold": 0.8, "count": int(cnt.item()),
+                           "pair_samples_per_s": pair_samples / (te * 1e-3)}
+        del z32
+
+    # CPU baseline and accuracy on the same check blocks
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cb, blocks = cpu_baseline(X, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        I = np.concatenate([b[0] for b in blocks])
+        J = np.concatenate([b[1] for b in blocks])
+        ref = np.concatenate([b[2] for b in blocks])
+        length = (n - 1 - np.arange(n, dtype=np.int64))
+        start = np.concatenate([[0], np.cumsum(length)[:-1]])
+        pos = torch.from_numpy(start[I] + (J - I - 1)).to(dev)
+        acc = {}
+        for m in ("split", "fp32", "bf16", "fp16"):
+            zdm = pcc.z_layout(n, l, m)
+            zm = torch.empty(zdm.bytes, dtype=torch.uint8, device=dev)
+            pcc.normalize(x, m, z=zm)
+            pcc.allpairs(zm, zdm, pcc.default_cfg(zdm), out=r)
+            got = r[pos].cpu().numpy().astype(np.float64)
+            acc[m] = float(np.max(np.abs(got - ref)))
+            del zm
+        extras["max_abs_dr_vs_fp64_oracle"] = {"pairs": int(len(I)), **acc}
+    else:
+        out["cpu_baseline"] = None
+
+    if not args.no_extras:
+        del r
+        torch.cuda.empty_cache()
+        extras.update(bench_permtest(pcc, workloads, stream, dev))
+        extras.update(bench_batched(pcc, workloads, stream, dev))
+        extras.update(bench_big_edges(pcc, workloads, stream, dev))
+    out["extras"] = extras
+    print(json.dumps(out), flush=True)
+
+
+def bench_permtest(pcc, workloads, stream, dev):
+    import torch
+    log("[bench] permutation test n=8192 l=512 P=1000")
+    X, _, perms = workloads.config4()
+    n, l = X.shape
+    P = perms.shape[0]
+    x = torch.from_numpy(X).to(dev)
+    z, zd = pcc.normalize(x, "fp32")
+    pt = torch.from_numpy(perms).to(dev)
+    counts = torch.empty(n * (n - 1) // 2, dtype=torch.int32, device=dev)
+    pcc.permtest(z, zd, pt[:8], out=counts)   # warm-up with a few permutations
+    ms, _ = timed(lambda: pcc.permtest(z, zd, pt, out=counts), 2, stream)
+    ps = (n * (n - 1) // 2) * l * (P + 1)
+    return {"permtest": {"workload": f"n={n} l={l} P={P} FP32 MFMA, one launch", "ms": ms,
+                         "pair_samples_per_s": ps / (ms * 1e-3),
+                         "mfma_frac": 2.0 * ps / (ms * 1e-3) / PEAK["fp32"]}}
+
+
+def bench_batched(pcc, workloads, stream, dev):
+    import torch
+    log("[bench] uneven batch of 64 datasets")
+    batch = workloads.config5_batch()
+    xs = [torch.from_numpy(X).to(dev) for X, _ in batch]
+    plan = pcc.BatchPlan(xs, "split")
+    plan.launch()
+    torch.cuda.synchronize()
+    ms, _ = timed(plan.launch, 3, stream)
+    ps = sum((X.shape[0] * (X.shape[0] - 1) // 2) * X.shape[1] for X, _ in batch)
+    res = {"batched": {"workload": "64 datasets n~U[500,8000] l~U[50,2000], split, one graph "
+                                   "(normalise + persistent all-pairs)", "ms": ms,
+                       "pair_samples_per_s": ps / (ms * 1e-3),
+                       "mfma_frac": 6.0 * ps / (ms * 1e-3) / PEAK["bf16"], "jobs": plan.jobs}}
+    plan.close()
+    return res
+
+
+def bench_big_edges(pcc, workloads, stream, dev):
+    import torch
+    log("[bench] n=65536 l=2048 split edges |r|>=0.9")
+    X, _ = workloads.config5_big()
+    n, l = X.shape
+    x = torch.from_numpy(X).to(dev)
+    del X
+    z, zd = pcc.normalize(x, "split")
+    del x
+    cfg = pcc.default_cfg(zd)
+    ij, rv, c = pcc.threshold_edges(z, zd, 0.9, 1 << 16, cfg)
+    ms, _ = timed(lambda: pcc.threshold_edges(z, zd, 0.9, 1 << 16, cfg, sync=False), 3, stream)
+    ps = (n * (n - 1) // 2) * l
+    return {"big_edges": {"workload": f"n={n} l={l} split, |r|>=0.9 edge list", "ms": ms,
+                          "edges": c, "pair_samples_per_s": ps / (ms * 1e-3),
+                          "mfma_frac": 6.0 * ps / (ms * 1e-3) / PEAK["bf16"]}}
+
+
+if __name__ == "__main__":
+    main()
