@@ -113,6 +113,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline step only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run a plain 1 GiB device copy (twice) whose "
+                         "known traffic calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the all-pairs path "
@@ -169,6 +172,16 @@ def main():
     tile_ms = [a.elapsed_time(b) for a, b in ev]
     tile_avg = float(np.mean(tile_ms))
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, tile kernel {tile_avg:.3f} ms")
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 2 x 1 GiB device-to-device copies")
+        del src, dst
 
     pair_samples = npairs * l
     value = pair_samples / (ms_step * 1e-3)
