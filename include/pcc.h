@@ -107,7 +107,8 @@ const char *pcc_status_string(pcc_status s);
 int32_t pcc_version(void);
 
 /* Fill *out with the Z layout for n profiles of l samples in `mode`.
- * Host only, pure.  Requires 2 <= n <= 2^31-1 and 2 <= l <= 2^24. */
+ * Host only, pure.  Requires 2 <= n <= 2^31-1 and 2 <= l <= 2^22 (a
+ * 256-row panel of Z stays below 4 GiB, so tile loads use 32-bit offsets). */
 pcc_status pcc_z_layout(int64_t n, int64_t l, pcc_mode_t mode, pcc_zdesc *out);
 
 /* Default tile schedule for a layout (host only, pure). */

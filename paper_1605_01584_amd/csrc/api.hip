@@ -27,7 +27,7 @@ int64_t permtest_max_l(int mode);
 namespace {
 
 constexpr int64_t kMaxN = 2147483647LL;  // (i, j) of an edge are int32
-constexpr int64_t kMaxL = 1LL << 24;
+constexpr int64_t kMaxL = 1LL << 22;  // 256 rows of Z stay within 4 GiB (32-bit offsets)
 
 bool valid_mode(int m) { return m >= PCC_FP32 && m <= PCC_FP16; }
 

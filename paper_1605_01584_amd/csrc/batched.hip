@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void batch_norm_kernel(const BatchDesc *__rest
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256, 1) void batch_tile_kernel(const BatchDesc *__restrict__ descs,
+__global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const BatchDesc *__restrict__ descs,
                                                             int D, int64_t total_jobs,
                                                             unsigned long long *counter) {
   __shared__ u32x4 smem[TileShape<256>::LDS_UNITS];
@@ -124,7 +124,7 @@ hipError_t launch_batch(const BatchDesc *descs, int D, int64_t total_rows, int64
   int64_t grid = cus;
   if (grid > total_jobs) grid = total_jobs;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((batch_tile_kernel<MODE>), dim3((unsigned)grid), dim3(256), 0, st, descs, D,
+  hipLaunchKernelGGL((batch_tile_kernel<MODE>), dim3((unsigned)grid), dim3(kTileThreads), 0, st, descs, D,
                      total_jobs, counter);
   return hipGetLastError();
 }

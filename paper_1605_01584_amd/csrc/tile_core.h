@@ -2,23 +2,33 @@
 // kernels (tiles.hip) and the uneven-batch kernel (batched.hip).
 //
 // One call computes one TILE x TILE tile (yt, xt) of Z Z^T (Eq. (5)) with a
-// 256-thread workgroup: 4 waves in a 2 x 2 grid, each wave a (TILE/2)^2
-// block of 32 x 32 MFMA blocks with FP32 accumulators in registers for the
-// whole K loop.  K loop: one 128-byte chunk of every row per stage (32 FP32
-// samples, 32 split hi+lo samples, or 64 BF16/FP16 samples), staged
-// global -> VGPR -> LDS, double buffered with one barrier per stage.  In LDS
-// a row is 8 units of 16 bytes, unit u of row r at slot u ^ (r & 7), so the
-// ds_read_b128 of 32 rows by a half-wave hit distinct banks.
+// 512-thread workgroup: 8 waves, two per SIMD, in a 4 x 2 grid, each wave a
+// (TILE/4) x (TILE/2) block of 32 x 32 MFMA blocks whose FP32 accumulators
+// stay in registers for the whole K loop.  Two waves per SIMD let one wave's
+// LDS reads and barrier waits overlap the other's MFMAs.
+//
+// K loop: one 128-byte chunk of every row per stage (32 FP32 samples, 32
+// split hi+lo samples, or 64 BF16/FP16 samples).  Stages are copied global ->
+// LDS directly by buffer_load ... lds (no VGPR staging), double buffered.
+// In LDS a row is 8 units of 16 bytes, unit u of row r at slot
+// u ^ ((r & 7) ^ ((r >> 3) & 1)): the ds_read_b128 of 16 consecutive rows hit
+// 16 distinct bank groups, so fragment reads are conflict free.
+//
+// Each stage is split in two halves of fragments; the second half is read
+// while the first half's MFMAs run, and the next stage's first half is read
+// (after the stage barrier) while the second half's MFMAs run:
+//   read h1(c) | MFMA h0(c) | wait DMA(c+1), barrier, read h0(c+1),
+//   DMA(c+2) into the buffer stage c used | MFMA h1(c)
 //
 // Sample assignment inside a chunk (any assignment works as long as both
 // operands use the same one, since the contraction sums over all samples):
-//   FP32   step t = 0..3, lane half g reads unit 2t+g (4 samples) and feeds
-//          them to 4 consecutive 32x32x2 MFMAs (K = 2: one sample per half);
-//   BF16/FP16  step t = 0..3, half g reads unit 2t+g (8 samples), one
-//          32x32x16 MFMA;
-//   SPLIT  step t = 0..1, half g reads hi unit 2t+g and lo unit 4+2t+g of
-//          the same 8 samples; three 32x32x16 MFMAs lo.hi + hi.lo + hi.hi
-//          into one FP32 accumulator (the lo.lo term, ~2^-16 of r, dropped).
+//   FP32   fragment (h, s) = unit 2(2h+s)+g, 4 samples feeding 4 consecutive
+//          32x32x2 MFMAs (K = 2: one sample per lane half g);
+//   BF16/FP16  fragment (h, s) = unit 2(2h+s)+g (8 samples), one 32x32x16
+//          MFMA each;
+//   SPLIT  half h: hi unit 2h+g and lo unit 4+2h+g of the same 8 samples;
+//          three 32x32x16 MFMAs lo.hi + hi.lo + hi.hi into one FP32
+//          accumulator (the lo.lo term, about 2^-16 of r, is dropped).
 #pragma once
 
 #include "pcc_internal.h"
@@ -30,8 +40,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void;
 
 enum { EPI_PACKED = 0, EPI_EDGES = 1 };
+
+constexpr int kTileThreads = 512;  // 8 waves
+constexpr int kWavesR = 4, kWavesC = 2;
 
 // Z operand of one tile computation.
 struct ZView {
@@ -53,11 +67,13 @@ struct EpiArgs {
 };
 
 template <int TILE> struct TileShape {
-  static constexpr int WT = TILE / 2;    // wave tile side
-  static constexpr int NB = WT / 32;     // MFMA blocks per wave side
-  static constexpr int OPU = TILE * 8;   // LDS units per operand per stage
-  static constexpr int LPT = OPU / 256;  // units per thread per operand
-  static constexpr int LDS_UNITS = 2 * 2 * OPU;  // [buffer][A | B]
+  static constexpr int WTR = TILE / kWavesR;  // wave tile rows
+  static constexpr int WTC = TILE / kWavesC;  // wave tile columns
+  static constexpr int NBR = WTR / 32;        // MFMA blocks per wave, rows
+  static constexpr int NBC = WTC / 32;        // MFMA blocks per wave, columns
+  static constexpr int OPU = TILE * 8;        // LDS units per operand per stage
+  static constexpr int IPW = OPU / 64 / (kWavesR * kWavesC);  // DMA per wave per operand
+  static constexpr int LDS_UNITS = 2 * 2 * OPU;               // [buffer][A | B]
 };
 
 __device__ __forceinline__ float clamp_unit(float r) {
@@ -65,159 +81,188 @@ __device__ __forceinline__ float clamp_unit(float r) {
   return r > 1.0f ? 1.0f : (r < -1.0f ? -1.0f : r);
 }
 
+__device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
+  // Workgroups are dispatched to the 8 XCDs round robin (b % 8); give the
+  // workgroups of one XCD consecutive job ids so they share L2 lines.
+  return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+}
+
+__device__ __forceinline__ int lds_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+// LDS unit of fragment s of half h for lane half g.
+template <int MODE> __device__ __forceinline__ int frag_unit(int h, int s, int g) {
+  if constexpr (MODE == PCC_SPLIT_BF16X3)
+    return s * 4 + 2 * h + g;  // s = 0: hi, s = 1: lo
+  else
+    return 2 * (2 * h + s) + g;
+}
+
 template <int MODE, int NB>
-__device__ __forceinline__ void mma_stage(const u32x4 *__restrict__ sa, const u32x4 *__restrict__ sb,
-                                          int i, int g, f32x16 (&acc)[NB][NB]) {
-  const int sw = i & 7;
+__device__ __forceinline__ void read_half(const u32x4 *__restrict__ base, int i, int g, int h,
+                                          u32x4 (&f)[2][NB]) {
+  const int sw = lds_swz(i);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int u = frag_unit<MODE>(h, s, g) ^ sw;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) f[s][q] = base[(q * 32 + i) * 8 + u];
+  }
+}
+
+template <int MODE, int NBR, int NBC>
+__device__ __forceinline__ void mfma_half(const u32x4 (&fa)[2][NBR], const u32x4 (&fb)[2][NBC],
+                                          f32x16 (&acc)[NBR][NBC]) {
   if constexpr (MODE == PCC_FP32) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int uu = (2 * t + g) ^ sw;
-      f32x4 a[NB], b[NB];
+    for (int s = 0; s < 2; ++s) {
+      // cast whole vectors, then index the floats
+      f32x4 a[NBR], b[NBC];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        a[q] = __builtin_bit_cast(f32x4, sa[(q * 32 + i) * 8 + uu]);
-        b[q] = __builtin_bit_cast(f32x4, sb[(q * 32 + i) * 8 + uu]);
-      }
+      for (int q = 0; q < NBR; ++q) a[q] = __builtin_bit_cast(f32x4, fa[s][q]);
+#pragma unroll
+      for (int q = 0; q < NBC; ++q) b[q] = __builtin_bit_cast(f32x4, fb[s][q]);
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int p = 0; p < NB; ++p)
+        for (int p = 0; p < NBR; ++p)
 #pragma unroll
-          for (int q = 0; q < NB; ++q)
+          for (int q = 0; q < NBC; ++q)
             acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p][e], b[q][e], acc[p][q], 0, 0, 0);
     }
   } else if constexpr (MODE == PCC_SPLIT_BF16X3) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int uh = (2 * t + g) ^ sw;
-      const int ul = (4 + 2 * t + g) ^ sw;
-      bf16x8 ah[NB], al[NB], bh[NB], bl[NB];
+    for (int p = 0; p < NBR; ++p)
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        ah[q] = __builtin_bit_cast(bf16x8, sa[(q * 32 + i) * 8 + uh]);
-        al[q] = __builtin_bit_cast(bf16x8, sa[(q * 32 + i) * 8 + ul]);
-        bh[q] = __builtin_bit_cast(bf16x8, sb[(q * 32 + i) * 8 + uh]);
-        bl[q] = __builtin_bit_cast(bf16x8, sb[(q * 32 + i) * 8 + ul]);
+      for (int q = 0; q < NBC; ++q) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, fa[0][p]);
+        const bf16x8 al = __builtin_bit_cast(bf16x8, fa[1][p]);
+        const bf16x8 bh = __builtin_bit_cast(bf16x8, fb[0][q]);
+        const bf16x8 bl = __builtin_bit_cast(bf16x8, fb[1][q]);
+        acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[p][q], 0, 0, 0);
+        acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[p][q], 0, 0, 0);
+        acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[p][q], 0, 0, 0);
       }
-#pragma unroll
-      for (int p = 0; p < NB; ++p)
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[p], bh[q], acc[p][q], 0, 0, 0);
-          acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[p], bl[q], acc[p][q], 0, 0, 0);
-          acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[p], bh[q], acc[p][q], 0, 0, 0);
-        }
-    }
   } else {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int uu = (2 * t + g) ^ sw;
-      u32x4 a[NB], b[NB];
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        a[q] = sa[(q * 32 + i) * 8 + uu];
-        b[q] = sb[(q * 32 + i) * 8 + uu];
-      }
+      for (int p = 0; p < NBR; ++p)
 #pragma unroll
-      for (int p = 0; p < NB; ++p)
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
+        for (int q = 0; q < NBC; ++q) {
           if constexpr (MODE == PCC_BF16)
             acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, a[p]), __builtin_bit_cast(bf16x8, b[q]), acc[p][q], 0, 0, 0);
+                __builtin_bit_cast(bf16x8, fa[s][p]), __builtin_bit_cast(bf16x8, fb[s][q]), acc[p][q], 0, 0, 0);
           else
             acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(f16x8, a[p]), __builtin_bit_cast(f16x8, b[q]), acc[p][q], 0, 0, 0);
+                __builtin_bit_cast(f16x8, fa[s][p]), __builtin_bit_cast(f16x8, fb[s][q]), acc[p][q], 0, 0, 0);
         }
-    }
+  }
+}
+
+// Copy stage (byte offset cb within every row) of both panels into LDS at dst.
+// DMA instruction inst fills LDS units [64 inst, 64 inst + 64) of an operand:
+// rows 8 inst .. 8 inst + 7, lane l taking row 8 inst + l/8 and the unit that
+// belongs in slot l % 8.  Wave w issues instructions w * IPW .. + IPW - 1.
+template <int TILE>
+__device__ __forceinline__ void dma_stage(__amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rbs,
+                                          uint32_t lane_row_off, uint32_t uoff_even,
+                                          uint32_t uoff_odd, uint32_t row8_bytes, uint32_t cb,
+                                          u32x4 *dst, int w) {
+  using S = TileShape<TILE>;
+#pragma unroll
+  for (int k = 0; k < S::IPW; ++k) {
+    const int inst = w * S::IPW + k;
+    const uint32_t voff = lane_row_off + ((inst & 1) ? uoff_odd : uoff_even);
+    const uint32_t soff = (uint32_t)k * row8_bytes + cb;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void *)(dst + inst * 64), 16, voff, soff, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rbs, (lds_void *)(dst + S::OPU + inst * 64), 16, voff,
+                                             soff, 0, 0);
   }
 }
 
 // Compute tile (yt, xt) and write its strict-upper-triangle pairs.
-// Requires: all 256 threads of the workgroup call it together; smem holds
-// TileShape<TILE>::LDS_UNITS units; rows yt*TILE .. +TILE and xt*TILE ..
-// +TILE exist in Z (n_pad is a multiple of 256).
+// Requires: all 512 threads of the workgroup call it together; smem holds
+// TileShape<TILE>::LDS_UNITS units; rows yt*TILE .. +TILE and xt*TILE .. +TILE
+// exist in Z (n_pad is a multiple of 256); TILE * row_bytes <= 2^32.
 template <int MODE, int TILE, int EPI>
 __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int64_t yt, int64_t xt,
                                         u32x4 *__restrict__ smem) {
   using S = TileShape<TILE>;
-  constexpr int WT = S::WT, NB = S::NB, OPU = S::OPU, LPT = S::LPT;
+  constexpr int WTR = S::WTR, WTC = S::WTC, NBR = S::NBR, NBC = S::NBC, OPU = S::OPU;
+  constexpr int IPW = S::IPW;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;
+  const int wr = w / kWavesC, wc = w % kWavesC;
   const int i = lane & 31, g = lane >> 5;
+  const int64_t rb = zv.row_bytes;
+  const unsigned char *za = zv.z + yt * TILE * rb;
+  const unsigned char *zb = zv.z + xt * TILE * rb;
+  const __amdgpu_buffer_rsrc_t rsa =
+      __builtin_amdgcn_make_buffer_rsrc((void *)za, (short)0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsb =
+      __builtin_amdgcn_make_buffer_rsrc((void *)zb, (short)0, 0x7fffffff, 0x00020000);
+  const int ro = lane >> 3;
+  const uint32_t lane_row_off = (uint32_t)((8 * IPW * w + ro) * rb);
+  const uint32_t uoff_even = (uint32_t)(((lane & 7) ^ lds_swz(ro)) * 16);
+  const uint32_t uoff_odd = (uint32_t)(((lane & 7) ^ lds_swz(ro + 8)) * 16);
+  const uint32_t row8 = (uint32_t)(8 * rb);
+  const int nch = zv.nchunks;
+  const int aoff = (wr * WTR) * 8, boff = OPU + (wc * WTC) * 8;
 
-  const unsigned char *za = zv.z + yt * TILE * zv.row_bytes;
-  const unsigned char *zb = zv.z + xt * TILE * zv.row_bytes;
-
-  f32x16 acc[NB][NB];
+  f32x16 acc[NBR][NBC];
 #pragma unroll
-  for (int p = 0; p < NB; ++p)
+  for (int p = 0; p < NBR; ++p)
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
+    for (int q = 0; q < NBC; ++q)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[p][q][v] = 0.0f;
 
-  // Thread tid stages rows tid/8 + 32 s (s < LPT), unit tid % 8: eight
-  // threads cover one 128-byte row chunk, so each load reads whole lines.
-  // Row r0 + 32 s keeps the swizzle of row r0, so slot and offset advance by
-  // constants with s.
-  const int u0 = tid & 7, r0 = tid >> 3;
-  const int64_t goff = (int64_t)r0 * zv.row_bytes + u0 * 16;
-  const int64_t gstep = 32 * zv.row_bytes;
-  const int lslot = r0 * 8 + (u0 ^ (r0 & 7));
-  u32x4 ra[LPT], rb[LPT];
-#pragma unroll
-  for (int s = 0; s < LPT; ++s) {
-    ra[s] = *reinterpret_cast<const u32x4 *>(za + goff + s * gstep);
-    rb[s] = *reinterpret_cast<const u32x4 *>(zb + goff + s * gstep);
-  }
-  __syncthreads();  // the previous tile's last reads of smem are done
-#pragma unroll
-  for (int s = 0; s < LPT; ++s) {
-    smem[lslot + 256 * s] = ra[s];
-    smem[OPU + lslot + 256 * s] = rb[s];
+  u32x4 f0a[2][NBR], f0b[2][NBC], f1a[2][NBR], f1b[2][NBC];
+  __syncthreads();  // every wave is done reading the previous tile's stages
+  dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8, 0u, smem, w);
+  if (nch > 1) {
+    dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8, 128u, smem + 2 * OPU, w);
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * IPW) : "memory");  // stage 0 landed
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   __syncthreads();
-  for (int c = 0; c < zv.nchunks; ++c) {
-    const int buf = c & 1;
-    const bool more = c + 1 < zv.nchunks;
-    if (more) {
-      const int64_t cb = (int64_t)(c + 1) * 128;
-#pragma unroll
-      for (int s = 0; s < LPT; ++s) {
-        ra[s] = *reinterpret_cast<const u32x4 *>(za + goff + s * gstep + cb);
-        rb[s] = *reinterpret_cast<const u32x4 *>(zb + goff + s * gstep + cb);
-      }
+  read_half<MODE, NBR>(smem + aoff, i, g, 0, f0a);
+  read_half<MODE, NBC>(smem + boff, i, g, 0, f0b);
+  for (int c = 0; c < nch; ++c) {
+    const u32x4 *cur = smem + (c & 1) * 2 * OPU;
+    read_half<MODE, NBR>(cur + aoff, i, g, 1, f1a);
+    read_half<MODE, NBC>(cur + boff, i, g, 1, f1b);
+    mfma_half<MODE, NBR, NBC>(f0a, f0b, acc);
+    if (c + 1 < nch) {
+      // own DMA of stage c+1 landed and own reads of stage c returned; the
+      // barrier makes both true for every wave
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+      __syncthreads();
+      const u32x4 *nxt = smem + ((c + 1) & 1) * 2 * OPU;
+      read_half<MODE, NBR>(nxt + aoff, i, g, 0, f0a);
+      read_half<MODE, NBC>(nxt + boff, i, g, 0, f0b);
+      if (c + 2 < nch)
+        dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8,
+                        (uint32_t)(c + 2) * 128u, smem + (c & 1) * 2 * OPU, w);
     }
-    const u32x4 *base = smem + buf * 2 * OPU;
-    mma_stage<MODE, NB>(base + (wr * WT) * 8, base + OPU + (wc * WT) * 8, i, g, acc);
-    if (more) {
-      u32x4 *nb = smem + (buf ^ 1) * 2 * OPU;
-#pragma unroll
-      for (int s = 0; s < LPT; ++s) {
-        nb[lslot + 256 * s] = ra[s];
-        nb[OPU + lslot + 256 * s] = rb[s];
-      }
-    }
-    __syncthreads();
+    mfma_half<MODE, NBR, NBC>(f1a, f1b, acc);
   }
 
   // Epilogue.  Lane holds column x0 + 32q + i of block (p, q); accumulator
   // register v holds row 8*(v/4) + 4*g + (v%4) of the block.  Row y of the
   // packed triangle starts at F_{n-1}(y) - y - 1 + x.
   const int64_t n = zv.n;
-  const int64_t y0 = yt * TILE + wr * WT;
-  const int64_t x0 = xt * TILE + wc * WT;
+  const int64_t y0 = yt * TILE + wr * WTR;
+  const int64_t x0 = xt * TILE + wc * WTC;
 #pragma unroll
-  for (int p = 0; p < NB; ++p) {
+  for (int p = 0; p < NBR; ++p) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
       const int64_t rowbase = tri_F(n - 1, y) - 1 - y;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
+      for (int q = 0; q < NBC; ++q) {
         const int64_t x = x0 + q * 32 + i;
         if (y < x && x < n) {
           const float rv = clamp_unit(acc[p][q][v] * zv.scale);
@@ -237,12 +282,6 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
       }
     }
   }
-}
-
-__device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
-  // Workgroups are dispatched to the 8 XCDs round robin (b % 8); give the
-  // workgroups of one XCD consecutive job ids so they share L2 lines.
-  return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
 }
 
 }  // namespace pcc

@@ -21,7 +21,7 @@ struct UniformArgs {
 };
 
 template <int MODE, int TILE, int EPI>
-__global__ __launch_bounds__(256, 1) void tile_kernel(UniformArgs a) {
+__global__ __launch_bounds__(kTileThreads, 1) void tile_kernel(UniformArgs a) {
   __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
   const int64_t G = gridDim.x;
   for (int64_t J = xcd_slot(blockIdx.x, G); J < a.njobs; J += G) {
@@ -79,7 +79,7 @@ hipError_t launch(const pcc_zdesc &zd, UniformArgs a, int tile, int epi, int gri
   const void *k = kernel_for(zd.mode, tile, epi);
   if (!k) return hipErrorInvalidValue;
   void *args[] = {(void *)&a};
-  return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, st);
+  return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, st);
 }
 
 }  // namespace
@@ -90,7 +90,7 @@ int tile_occupancy(int mode, int tile, int epi) {
   int &c = cache[mode][tile == 128 ? 0 : 1][epi ? 1 : 0];
   if (c == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_for(mode, tile, epi), 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_for(mode, tile, epi), kTileThreads, 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;

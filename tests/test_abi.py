@@ -48,7 +48,7 @@ def test_layout(mode, kchunk, elem, n, l):
 
 def test_layout_rejects():
     import paper_1605_01584_amd as pcc
-    for n, l in [(1, 10), (0, 10), (10, 1), (10, 0), (2 ** 31, 10), (10, 2 ** 24 + 1)]:
+    for n, l in [(1, 10), (0, 10), (10, 1), (10, 0), (2 ** 31, 10), (10, 2 ** 22 + 1)]:
         with pytest.raises(pcc.PccError) as e:
             pcc.z_layout(n, l)
         assert e.value.status == pcc.PCC_E_SHAPE
