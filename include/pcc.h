@@ -162,17 +162,21 @@ pcc_status pcc_edges_status(int64_t count_host, int64_t cap);
  *   r_obs = Z_y . Z_x,  r_p = sum_k Z_y[k] Z_x[perm_p[k]],
  *   counts[J'] = #{p : |r_p| >= |r_obs|}  (ties counted; -1 if r_obs is NaN)
  * The second operand (column x) is permuted; Z's mean and norm are
- * invariant under a permutation, so Z is not renormalised.
- *   perms  device int32, P rows of l entries, each a permutation of 0..l-1
- *          (entries are not validated on the device; values outside
- *          [0, l) read zero padding or neighbouring samples).
+ * invariant under a permutation, so Z is not renormalised.  Jobs are 32 x 32
+ * pair blocks whose two profile panels stay in LDS for all P permutations.
+ *   perms  device int32, P rows of l entries, each a permutation of 0..l-1.
+ *          Not checked on the device: an entry outside [0, l) reads other
+ *          LDS contents of the job (never outside the workgroup's LDS), so
+ *          its counts are meaningless.  The Python binding checks them.
  *   counts device int32, n(n-1)/2.
- * Supported: mode FP32 or SPLIT_BF16X3, l_pad <= pcc_permtest_max_l(). */
+ * Supported: mode FP32 (the test compares |r| differences far below the
+ * 16-bit modes' error), l_pad <= pcc_permtest_max_l(PCC_FP32). */
 pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
                         const int32_t *perms, int32_t P, int32_t *counts,
                         void *workspace, void *stream);
 
-/* Largest l_pad pcc_permtest accepts (its column panel stays in LDS). */
+/* Largest l_pad pcc_permtest accepts (both 32-profile panels stay in LDS);
+ * 0 for modes it does not support. */
 int64_t pcc_permtest_max_l(pcc_mode_t mode);
 
 /* ---- Uneven batches (a7) ----------------------------------------------

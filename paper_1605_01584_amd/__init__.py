@@ -293,12 +293,18 @@ def threshold_edges(z, zd: ZDesc, thr: float, cap: int, cfg: Optional[TileCfg] =
     return ij[:c], rv[:c], c
 
 
-def permtest(z, zd: ZDesc, perms, out=None, stream=None):
-    """Counts of |r_perm| >= |r_obs| over the P rows of perms (device int32 P x l)."""
+def permtest(z, zd: ZDesc, perms, out=None, stream=None, validate: bool = True):
+    """Counts of |r_perm| >= |r_obs| over the P rows of perms (device int32 P x l).
+    validate=True checks on the device that every row is a permutation."""
     torch = _torch()
     if perms.dtype != torch.int32 or perms.dim() != 2 or perms.shape[1] != zd.l:
         raise ValueError("perms must be int32 (P, l)")
     perms = perms.contiguous()
+    if validate and perms.numel():
+        # every row must be a permutation of 0..l-1
+        srt = torch.sort(perms, dim=1).values
+        if not bool((srt == torch.arange(zd.l, device=perms.device, dtype=torch.int32)).all()):
+            raise ValueError("every row of perms must be a permutation of 0..l-1")
     npairs = zd.n * (zd.n - 1) // 2
     if out is None:
         out = torch.empty(npairs, dtype=torch.int32, device=z.device)
