@@ -301,9 +301,11 @@ def bench_permtest(pcc, workloads, stream, dev):
 def bench_batched(pcc, workloads, stream, dev):
     import torch
     log("[bench] uneven batch of 64 datasets")
+    from paper_1605_01584_amd import tune
     batch = workloads.config5_batch()
     xs = [torch.from_numpy(X).to(dev) for X, _ in batch]
-    plan = pcc.BatchPlan(xs, "split")
+    tiles, tune_ms = tune.tune_batch(xs, "split", use_cache=False)   # not timed
+    plan = pcc.BatchPlan(xs, "split", tiles=tiles)
     plan.launch()
     torch.cuda.synchronize()
     ms, _ = timed(plan.launch, 3, stream)
@@ -311,7 +313,9 @@ def bench_batched(pcc, workloads, stream, dev):
     res = {"batched": {"workload": "64 datasets n~U[500,8000] l~U[50,2000], split, one graph "
                                    "(normalise + persistent all-pairs)", "ms": ms,
                        "pair_samples_per_s": ps / (ms * 1e-3),
-                       "mfma_frac": 6.0 * ps / (ms * 1e-3) / PEAK["bf16"], "jobs": plan.jobs}}
+                       "mfma_frac": 6.0 * ps / (ms * 1e-3) / PEAK["bf16"], "jobs": plan.jobs,
+                       "tiles": {"256": tiles.count(256), "128": tiles.count(128)},
+                       "autotune_ms": tune_ms}}
     plan.close()
     return res
 

@@ -84,3 +84,27 @@ def test_config5_batch_sampled():
         total += n * (n - 1) // 2
     assert plan.jobs > 64
     plan.close()
+
+
+def test_autotuned_batch_matches_single(tmp_path, monkeypatch):
+    """The tuner's tile choice changes speed, never results."""
+    import torch
+    import paper_1605_01584_amd as pcc
+    from paper_1605_01584_amd import tune
+    monkeypatch.setenv("PCC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    Xs = _datasets([(300, 40), (1500, 64), (2600, 20)], 13)
+    xs = [to_device(X) for X in Xs]
+    tiles, times = tune.tune_batch(xs, "split", reps=2)
+    assert set(tiles) <= {128, 256} and len(tiles) == 3 and len(times) >= 3
+    again, _ = tune.tune_batch(xs, "split")       # served from the cache
+    assert again == tiles
+    plan = pcc.BatchPlan(xs, "split", tiles=tiles)
+    plan.launch()
+    torch.cuda.synchronize()
+    for d, X in enumerate(Xs):
+        z, zd = pcc.normalize(xs[d], "split")
+        single = pcc.allpairs(z, zd, pcc.TileCfg(tiles[d], 0, 1, 0))
+        assert torch.equal(plan.r[d], single)
+    plan.close()
+    cfg = tune.best_cfg(700, 50, "split", reps=1)
+    assert cfg.tile in (128, 256)
