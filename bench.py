@@ -102,6 +102,56 @@ def cpu_baseline(X, seconds=10.0):
     }, results
 
 
+def calibration(dev, stream):
+    """What this chip sustains, beside the nominal peaks the fractions use:
+    a register-only BF16 MFMA loop (libpcc_probe.so), a plain 1 GiB device
+    copy, and hipBLASLt's BF16 GEMM on the split path's operand shape (the
+    dense product Z Z^T with hi|lo concatenated along K), for context."""
+    import ctypes
+    import torch
+    import paper_1605_01584_amd as pcc
+    out = {}
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(pcc.__file__), "libpcc_probe.so"))
+    lib.pcc_probe_mfma_bf16.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+    lib.pcc_probe_mfma_bf16_flops.restype = ctypes.c_double
+    lib.pcc_probe_mfma_bf16_flops.argtypes = [ctypes.c_int, ctypes.c_int]
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks, iters = cus * 8, 20000
+    src = torch.randn(512, device=dev).to(torch.bfloat16)
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+
+    def probe():
+        if lib.pcc_probe_mfma_bf16(blocks, iters, ctypes.c_void_p(src.data_ptr()),
+                                   ctypes.c_void_p(sink.data_ptr()),
+                                   ctypes.c_void_p(stream.cuda_stream)) != 0:
+            raise RuntimeError("MFMA probe launch failed")
+    probe()
+    pm, _ = timed(probe, 3, stream)
+    fl = lib.pcc_probe_mfma_bf16_flops(blocks, iters)
+    out["mfma_loop_bf16"] = {"ms": pm, "TFLOP_per_s": fl / (pm * 1e-3) / 1e12,
+                             "frac_of_nominal": fl / (pm * 1e-3) / PEAK["bf16"]}
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    cm, _ = timed(lambda: b.copy_(a), 5, stream)
+    out["device_copy_1GiB"] = {"ms": cm, "GB_per_s": 2 * (1 << 30) / (cm * 1e-3) / 1e9,
+                               "frac_of_nominal": 2 * (1 << 30) / (cm * 1e-3) / HBM_PEAK}
+    del a, b
+    M, K = 32768, 8192
+    A = torch.randn(M, K, device=dev, dtype=torch.bfloat16)
+    Bt = A.t().contiguous()
+    C = torch.empty(M, M, device=dev, dtype=torch.bfloat16)
+    torch.matmul(A, Bt, out=C)
+    gm, _ = timed(lambda: torch.matmul(A, Bt, out=C), 3, stream)
+    out["hipblaslt_gemm_bf16"] = {"shape": f"{M}x{K} @ {K}x{M}", "ms": gm,
+                                  "TFLOP_per_s": 2.0 * M * M * K / (gm * 1e-3) / 1e12,
+                                  "frac_of_nominal": 2.0 * M * M * K / (gm * 1e-3) / PEAK["bf16"]}
+    del A, Bt, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +295,40 @@ def main():
         extras["edges"] = {"ms": te, "threshold": 0.8, "count": int(cnt.item()),
                            "pair_samples_per_s": pair_samples / (te * 1e-3)}
         del z32
+        del ij, rv
+        # FP64 tiles (the paper's precision), FP64 output
+        log("[bench] FP64 tile path")
+        zd64 = pcc.z_layout(n, l, "fp64")
+        z64 = torch.empty(zd64.bytes, dtype=torch.uint8, device=dev)
+        pcc.normalize(x, "fp64", z=z64)
+        r64 = torch.empty(npairs, dtype=torch.float64, device=dev)
+        cfg64 = pcc.default_cfg(zd64)
+        t64, _ = timed(lambda: pcc.allpairs_f64(z64, zd64, cfg64, out=r64), 3, stream)
+        extras["fp64_path"] = {
+            "tile_ms": t64, "pair_samples_per_s": pair_samples / (t64 * 1e-3),
+            "TFLOP_per_s": 2.0 * pair_samples / (t64 * 1e-3) / 1e12,
+            "mfma_frac": 2.0 * pair_samples / (t64 * 1e-3) / PEAK["fp64"],
+            "tile": cfg64.tile}
+        del z64, r64
+        torch.cuda.empty_cache()
+        # non-symmetric all pairs: the two halves of X against each other
+        log("[bench] non-symmetric X x Y")
+        h = n // 2
+        zdx = pcc.z_layout(h, l, mode)
+        zx = torch.empty(zdx.bytes, dtype=torch.uint8, device=dev)
+        zy = torch.empty(zdx.bytes, dtype=torch.uint8, device=dev)
+        pcc.normalize(x[:h], mode, z=zx)
+        pcc.normalize(x[h:2 * h], mode, z=zy)
+        rxy = torch.empty((h, h), dtype=torch.float32, device=dev)
+        txy, _ = timed(lambda: pcc.allpairs_xy(zx, zdx, zy, zdx, cfg, out=rxy), 3, stream)
+        ps_xy = float(h) * h * l
+        extras["xy"] = {"workload": f"{h} x {h} cross pairs, l={l}, {mode}", "ms": txy,
+                        "pair_samples_per_s": ps_xy / (txy * 1e-3),
+                        "mfma_frac": 2.0 * MFMA_PER_MAC[mode] * ps_xy / (txy * 1e-3) / PEAK[dt]}
+        del zx, zy, rxy
+        torch.cuda.empty_cache()
+        log("[bench] calibration: MFMA loop, device copy, hipBLASLt GEMM")
+        extras["calibration"] = calibration(dev, stream)
 
     # CPU baseline and accuracy on the same check blocks
     if not args.no_cpu:
@@ -266,6 +350,13 @@ def main():
             got = r[pos].cpu().numpy().astype(np.float64)
             acc[m] = float(np.max(np.abs(got - ref)))
             del zm
+        zd64 = pcc.z_layout(n, l, "fp64")
+        z64 = torch.empty(zd64.bytes, dtype=torch.uint8, device=dev)
+        pcc.normalize(x, "fp64", z=z64)
+        r64 = pcc.allpairs_f64(z64, zd64)
+        acc["fp64"] = float(np.max(np.abs(r64[pos].cpu().numpy() - ref)))
+        del z64, r64
+        torch.cuda.empty_cache()
         extras["max_abs_dr_vs_fp64_oracle"] = {"pairs": int(len(I)), **acc}
     else:
         out["cpu_baseline"] = None

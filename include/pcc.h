@@ -16,6 +16,8 @@
  *             transformation algorithm computes it)
  *   Eq. (5)   r(X_i, X_j) = U_i . U_j, so all pairs are A A^T with A = U,
  *             of which only the upper triangle is needed.
+ *   Eq. (7)-(8)   non-symmetric all-pairs: job id J = y n + x over the whole
+ *             job matrix (two different variable sets).
  *   Eq. (9)-(19)  direct bijective mapping between a job id and its
  *             upper-triangle cell, applied to t x t tiles (Sec. III-C).
  *
@@ -55,17 +57,22 @@ typedef enum {
 /* Element type of the input matrix X. */
 typedef enum { PCC_IN_F32 = 0, PCC_IN_F64 = 1 } pcc_in_t;
 
-/* Arithmetic of the tile contraction (all accumulate in FP32 on MFMA):
+/* Arithmetic of the tile contraction (FP32 accumulators on MFMA, except
+ * PCC_FP64):
  *   PCC_FP32          z in FP32, v_mfma_f32_32x32x2_f32.
  *   PCC_SPLIT_BF16X3  z = hi + lo with hi = bf16(z), lo = bf16(z - hi);
  *                     r = hi.hi + hi.lo + lo.hi, v_mfma_f32_32x32x16_bf16.
  *   PCC_BF16          z in BF16.
- *   PCC_FP16          z*sqrt(l) in FP16 (unit RMS entries), r = acc / l. */
+ *   PCC_FP16          z*sqrt(l) in FP16 (unit RMS entries), r = acc / l.
+ *   PCC_FP64          z in FP64, FP64 accumulators, v_mfma_f64_16x16x4_f64:
+ *                     the precision the paper computes in (its evaluation
+ *                     uses double throughout).  128-wide tiles only. */
 typedef enum {
   PCC_FP32 = 0,
   PCC_SPLIT_BF16X3 = 1,
   PCC_BF16 = 2,
-  PCC_FP16 = 3
+  PCC_FP16 = 3,
+  PCC_FP64 = 4
 } pcc_mode_t;
 
 /* Layout of the transformed matrix Z in device memory (written by
@@ -73,7 +80,8 @@ typedef enum {
  * row_bytes bytes.  A row is a sequence of 128-byte chunks, each holding
  * kchunk consecutive samples:
  *   FP32:  32 floats;             BF16 / FP16: 64 halves;
- *   SPLIT: 32 bf16 hi values followed by the 32 matching bf16 lo values.
+ *   SPLIT: 32 bf16 hi values followed by the 32 matching bf16 lo values;
+ *   FP64:  16 doubles.
  * Samples l..l_pad-1 and rows n..n_pad-1 are zero.  n_pad is a multiple of
  * 256 and l_pad a multiple of kchunk. */
 typedef struct {
@@ -86,7 +94,8 @@ typedef struct {
 } pcc_zdesc;
 
 /* Tile schedule of the all-pairs kernels.
- *   tile:  256 or 128, the side t of one tile job (Sec. III-C).
+ *   tile:  256 or 128, the side t of one tile job (Sec. III-C); PCC_FP64
+ *          supports 128 only.
  *   order: 0 = tile ids in the paper's order (row by row, Eq. (16)-(19));
  *          1 = banded order: the tile triangle is cut into bands of `band`
  *              tile rows; a band is walked column by column, so consecutive
@@ -107,8 +116,10 @@ const char *pcc_status_string(pcc_status s);
 int32_t pcc_version(void);
 
 /* Fill *out with the Z layout for n profiles of l samples in `mode`.
- * Host only, pure.  Requires 2 <= n <= 2^31-1 and 2 <= l <= 2^22 (a
- * 256-row panel of Z stays below 4 GiB, so tile loads use 32-bit offsets). */
+ * Host only, pure.  Requires 1 <= n <= 2^31-1 and 2 <= l <= 2^21 (a
+ * 256-row panel of Z stays within 2 GiB, so tile loads use 32-bit offsets).
+ * The symmetric entry points (all pairs of one set) need n >= 2 and return
+ * PCC_E_SHAPE otherwise; one profile against a set is pcc_allpairs_xy. */
 pcc_status pcc_z_layout(int64_t n, int64_t l, pcc_mode_t mode, pcc_zdesc *out);
 
 /* Default tile schedule for a layout (host only, pure). */
@@ -142,6 +153,12 @@ size_t pcc_workspace_size(const pcc_zdesc *zd, int32_t op);
 pcc_status pcc_allpairs(const pcc_zdesc *zd, const void *z, float *r,
                         const pcc_tile_cfg *cfg, void *workspace, void *stream);
 
+/* As pcc_allpairs, for zd->mode == PCC_FP64 only, with r written in FP64:
+ * r[J'] = clamp(Z_y . Z_x, -1, 1) as doubles (the paper's output
+ * precision).  r: device, n(n-1)/2 doubles. */
+pcc_status pcc_allpairs_f64(const pcc_zdesc *zd, const void *z, double *r,
+                            const pcc_tile_cfg *cfg, void *workspace, void *stream);
+
 /* Thresholded edge list (a4 (ii)): every pair y < x with |r| >= thr (r
  * clamped as above; NaN never qualifies) is appended as ij[2s] = y,
  * ij[2s+1] = x, rv[s] = r for a slot s < cap.  *count (device int64) is
@@ -156,6 +173,28 @@ pcc_status pcc_threshold_edges(const pcc_zdesc *zd, const void *z, float thr,
 /* Host helper after pcc_threshold_edges has completed: PCC_OK if
  * count <= cap, PCC_E_CAPACITY otherwise (count read from host memory). */
 pcc_status pcc_edges_status(int64_t count_host, int64_t cap);
+
+/* Non-symmetric all pairs, Eq. (7)-(8): two variable sets X (nx profiles)
+ * and Y (ny profiles) with the same number of samples, each transformed by
+ * pcc_normalize in the same mode (zdx->l == zdy->l, zdx->mode == zdy->mode).
+ * Every cell of the nx x ny job matrix is a job; tile jobs are numbered
+ * J = yt mc + xt over the mx x mc tile rectangle (cfg->order 0) or in bands
+ * of cfg->band tile rows walked column by column (order 1).
+ *   r[y * ldr + x] = clamp(ZX_y . ZY_x, -1, 1)  for 0 <= y < nx, 0 <= x < ny
+ * r: device, nx rows of pitch ldr >= ny floats (entries x >= ny untouched).
+ * zx and zy may be the same buffer (then r is the full symmetric matrix,
+ * diagonal included). */
+pcc_status pcc_allpairs_xy(const pcc_zdesc *zdx, const void *zx, const pcc_zdesc *zdy,
+                           const void *zy, float *r, int64_t ldr,
+                           const pcc_tile_cfg *cfg, void *workspace, void *stream);
+
+/* Thresholded edges of the non-symmetric job matrix: every (y, x) with
+ * |r| >= thr, y indexing X and x indexing Y; otherwise as
+ * pcc_threshold_edges (unordered, *count is the true total). */
+pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
+                                  const pcc_zdesc *zdy, const void *zy, float thr,
+                                  int32_t *ij, float *rv, int64_t cap, int64_t *count,
+                                  const pcc_tile_cfg *cfg, void *workspace, void *stream);
 
 /* Permutation test (a6), one persistent launch for all P permutations.
  * For every pair y < x:
@@ -203,7 +242,8 @@ size_t pcc_batch_workspace_size(int32_t D);
 
 /* Build a plan (host work + one synchronous upload of the descriptor table
  * on `stream`).  Items must stay valid for the plan's life; all items use
- * `mode`. */
+ * `mode` (PCC_FP32, PCC_SPLIT_BF16X3, PCC_BF16 or PCC_FP16; PCC_FP64 gives
+ * PCC_E_MODE) and have n >= 2. */
 pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items,
                                  pcc_mode_t mode, void *workspace,
                                  size_t workspace_bytes, void *stream,
@@ -232,6 +272,10 @@ pcc_status pcc_cells_host(int64_t m, int32_t diag, int64_t J0, int64_t count,
  * starting at J0 under cfg->order/cfg->band over an m x m tile triangle. */
 pcc_status pcc_tile_order_host(int64_t m, const pcc_tile_cfg *cfg, int64_t J0,
                                int64_t count, int64_t *yt, int64_t *xt);
+/* Tile order of a non-symmetric schedule over an mr x mc tile rectangle
+ * (Eq. (7)-(8) for order 0, bands of cfg->band tile rows for order 1). */
+pcc_status pcc_rect_tile_order_host(int64_t mr, int64_t mc, const pcc_tile_cfg *cfg,
+                                    int64_t J0, int64_t count, int64_t *yt, int64_t *xt);
 /* Device form of pcc_cells_host, computed by the same device code the tile
  * kernels use; y and x are device arrays of `count` entries. */
 pcc_status pcc_cells_device(int64_t m, int32_t diag, int64_t J0, int64_t count,

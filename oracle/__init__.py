@@ -36,6 +36,8 @@ def _load():
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_pearson_packed.argtypes = [_dp, _i64, _i64, _i64, _dp]
     lib.oracle_pearson_packed.restype = ctypes.c_int
+    lib.oracle_pearson_xy.argtypes = [_dp, _i64, _i64, _dp, _i64, _i64, _i64, _dp]
+    lib.oracle_pearson_xy.restype = ctypes.c_int
     lib.oracle_pearson_pairs.argtypes = [_dp, _i64, _i64, _i64, _lp, _lp, _i64, _dp]
     lib.oracle_pearson_pairs.restype = ctypes.c_int
     lib.oracle_transform.argtypes = [_dp, _i64, _i64, _i64, _dp, _dp, _dp]
@@ -77,6 +79,21 @@ def pearson_packed(X) -> np.ndarray:
     rc = _load().oracle_pearson_packed(_ptr(X, _dp), n, l, l, _ptr(out, _dp))
     if rc != 0:
         raise RuntimeError(f"oracle_pearson_packed: {rc}")
+    return out
+
+
+def pearson_xy(X, Y) -> np.ndarray:
+    """Non-symmetric all pairs: r[i, j] = r(X_i, Y_j), an nx x ny FP64 matrix."""
+    X = _f64(X)
+    Y = _f64(Y)
+    nx, l = X.shape
+    ny, ly = Y.shape
+    if ly != l:
+        raise ValueError("X and Y must have the same number of samples")
+    out = np.empty((nx, ny), dtype=np.float64)
+    rc = _load().oracle_pearson_xy(_ptr(X, _dp), nx, l, _ptr(Y, _dp), ny, l, l, _ptr(out, _dp))
+    if rc != 0:
+        raise RuntimeError(f"oracle_pearson_xy: {rc}")
     return out
 
 

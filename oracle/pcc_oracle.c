@@ -13,6 +13,8 @@
  *     in the denominator (as the variable-transformation algorithm computes
  *     it): mean, sum of squared deviations, reciprocal square root, scaled
  *     deviations;
+ *   - non-symmetric all-pairs (two variable sets, Sec. III-A) is Eq. (1)
+ *     for every cell of the nx x ny job matrix, row by row;
  *   - job numbering follows the symmetric all-pairs framework (Sec. III-B):
  *     upper-triangle cells numbered left to right, top to bottom, by
  *     counting, never by the closed-form map;
@@ -97,6 +99,18 @@ int oracle_pearson_packed(const double *X, int64_t n, int64_t l, int64_t ld,
     for (int64_t j = i + 1; j < n; ++j) out[t++] = pearson_literal(X + i * ld, X + j * ld, l);
   }
   free(start);
+  return 0;
+}
+
+/* Non-symmetric all-pairs (Sec. III-A): r of row i of X (nx rows, pitch
+ * ldx) and row j of Y (ny rows, pitch ldy), both of l samples, written to
+ * out[i * ny + j] for every i and j (the whole job matrix, row by row). */
+int oracle_pearson_xy(const double *X, int64_t nx, int64_t ldx, const double *Y, int64_t ny,
+                      int64_t ldy, int64_t l, double *out) {
+  if (!X || !Y || !out || nx < 0 || ny < 0 || l < 1 || ldx < l || ldy < l) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nx; ++i)
+    for (int64_t j = 0; j < ny; ++j) out[i * ny + j] = pearson_literal(X + i * ldx, Y + j * ldy, l);
   return 0;
 }
 

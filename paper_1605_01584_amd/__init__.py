@@ -6,7 +6,8 @@ used for device memory and streams.  Importing this package fails loudly if
 the library has not been built (``python -m paper_1605_01584_amd.build``).
 
 Names follow the C ABI: ``z_layout``, ``normalize``, ``allpairs``,
-``threshold_edges``, ``permtest``, ``BatchPlan``, the job maps and
+``allpairs_f64``, ``threshold_edges``, ``allpairs_xy``,
+``threshold_edges_xy``, ``permtest``, ``BatchPlan``, the job maps and
 ``autotune``.
 """
 from __future__ import annotations
@@ -31,8 +32,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 PCC_OK, PCC_E_ARG, PCC_E_SHAPE, PCC_E_MODE, PCC_E_CAPACITY, PCC_E_HIP, PCC_E_WORKSPACE, \
     PCC_E_DEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 IN_F32, IN_F64 = 0, 1
-FP32, SPLIT_BF16X3, BF16, FP16 = 0, 1, 2, 3
-MODES = {"fp32": FP32, "split": SPLIT_BF16X3, "bf16": BF16, "fp16": FP16}
+FP32, SPLIT_BF16X3, BF16, FP16, FP64 = 0, 1, 2, 3, 4
+MODES = {"fp32": FP32, "split": SPLIT_BF16X3, "bf16": BF16, "fp16": FP16, "fp64": FP64}
 
 
 class ZDesc(ctypes.Structure):
@@ -82,7 +83,11 @@ _sig("pcc_default_cfg", _i32, _zdp, _cfgp)
 _sig("pcc_normalize", _i32, _vp, _i32, _i64, _zdp, _vp, _vp, _vp, _vp)
 _sig("pcc_workspace_size", ctypes.c_size_t, _zdp, _i32)
 _sig("pcc_allpairs", _i32, _zdp, _vp, _vp, _cfgp, _vp, _vp)
+_sig("pcc_allpairs_f64", _i32, _zdp, _vp, _vp, _cfgp, _vp, _vp)
 _sig("pcc_threshold_edges", _i32, _zdp, _vp, _f32, _vp, _vp, _i64, _vp, _cfgp, _vp, _vp)
+_sig("pcc_allpairs_xy", _i32, _zdp, _vp, _zdp, _vp, _vp, _i64, _cfgp, _vp, _vp)
+_sig("pcc_threshold_edges_xy", _i32, _zdp, _vp, _zdp, _vp, _f32, _vp, _vp, _i64, _vp, _cfgp, _vp,
+     _vp)
 _sig("pcc_edges_status", _i32, _i64, _i64)
 _sig("pcc_permtest", _i32, _zdp, _vp, _vp, _i32, _vp, _vp, _vp)
 _sig("pcc_permtest_max_l", _i64, _i32)
@@ -98,13 +103,15 @@ _sig("pcc_packed_index", _i64, _i64, _i64, _i64)
 _sig("pcc_packed_cell", None, _i64, _i64, _i64p, _i64p)
 _sig("pcc_cells_host", _i32, _i64, _i32, _i64, _i64, _vp, _vp)
 _sig("pcc_tile_order_host", _i32, _i64, _cfgp, _i64, _i64, _vp, _vp)
+_sig("pcc_rect_tile_order_host", _i32, _i64, _i64, _cfgp, _i64, _i64, _vp, _vp)
 _sig("pcc_cells_device", _i32, _i64, _i32, _i64, _i64, _vp, _vp, _vp)
 _sig("pcc_autotune", _i32, _zdp, _vp, _vp, _cfgp, _i32, _i32, _cfgp, _vp, _vp)
 _sig("pcc_device_cus", _i32)
 
 EXPORTED = [
     "pcc_status_string", "pcc_version", "pcc_z_layout", "pcc_default_cfg", "pcc_normalize",
-    "pcc_workspace_size", "pcc_allpairs", "pcc_threshold_edges", "pcc_edges_status",
+    "pcc_workspace_size", "pcc_allpairs", "pcc_allpairs_f64", "pcc_threshold_edges",
+    "pcc_edges_status", "pcc_allpairs_xy", "pcc_threshold_edges_xy", "pcc_rect_tile_order_host",
     "pcc_permtest", "pcc_permtest_max_l", "pcc_batch_workspace_size", "pcc_batch_plan_create",
     "pcc_batch_plan_launch", "pcc_batch_plan_jobs", "pcc_batch_plan_destroy", "pcc_job_of_cell",
     "pcc_cell_of_job", "pcc_packed_index", "pcc_packed_cell", "pcc_cells_host",
@@ -191,6 +198,14 @@ def tile_order_host(m: int, cfg: TileCfg, J0: int, count: int):
     return y, x
 
 
+def rect_tile_order_host(mr: int, mc: int, cfg: TileCfg, J0: int, count: int):
+    y = np.empty(count, dtype=np.int64)
+    x = np.empty(count, dtype=np.int64)
+    _check(_lib.pcc_rect_tile_order_host(mr, mc, ctypes.byref(cfg), J0, count, y.ctypes.data,
+                                         x.ctypes.data), "pcc_rect_tile_order_host")
+    return y, x
+
+
 def permtest_max_l(mode="fp32") -> int:
     return _lib.pcc_permtest_max_l(_mode(mode))
 
@@ -269,6 +284,57 @@ def allpairs(z, zd: ZDesc, cfg: Optional[TileCfg] = None, out=None, stream=None)
                              ctypes.byref(cfg) if cfg is not None else None, None,
                              _stream(torch, stream)), "pcc_allpairs")
     return out
+
+
+def allpairs_f64(z, zd: ZDesc, cfg: Optional[TileCfg] = None, out=None, stream=None):
+    """FP64 mode only: packed strict upper triangle of r in FP64."""
+    torch = _torch()
+    npairs = zd.n * (zd.n - 1) // 2
+    if out is None:
+        out = torch.empty(npairs, dtype=torch.float64, device=z.device)
+    elif out.numel() < npairs or out.dtype != torch.float64:
+        raise ValueError("out must hold n(n-1)/2 float64")
+    _check(_lib.pcc_allpairs_f64(ctypes.byref(zd), _dev_ptr(z, "z"), _dev_ptr(out, "r"),
+                                 ctypes.byref(cfg) if cfg is not None else None, None,
+                                 _stream(torch, stream)), "pcc_allpairs_f64")
+    return out
+
+
+def allpairs_xy(zx, zdx: ZDesc, zy, zdy: ZDesc, cfg: Optional[TileCfg] = None, out=None,
+                stream=None):
+    """Non-symmetric all pairs (Eq. 7-8): r[y, x] = r(X_y, Y_x), an nx x ny FP32
+    matrix (out may be a wider row-major matrix; its row pitch is used)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((zdx.n, zdy.n), dtype=torch.float32, device=zx.device)
+    if (out.dtype != torch.float32 or out.dim() != 2 or out.shape[0] < zdx.n
+            or out.shape[1] < zdy.n or out.stride(1) != 1):
+        raise ValueError("out must be float32 (>= nx, >= ny) with unit column stride")
+    _check(_lib.pcc_allpairs_xy(ctypes.byref(zdx), _dev_ptr(zx, "zx"), ctypes.byref(zdy),
+                                _dev_ptr(zy, "zy"), _dev_ptr(out, "r"), out.stride(0),
+                                ctypes.byref(cfg) if cfg is not None else None, None,
+                                _stream(torch, stream)), "pcc_allpairs_xy")
+    return out
+
+
+def threshold_edges_xy(zx, zdx: ZDesc, zy, zdy: ZDesc, thr: float, cap: int,
+                       cfg: Optional[TileCfg] = None, stream=None, sync: bool = True):
+    """Edges (y in X, x in Y) with |r| >= thr; as threshold_edges."""
+    torch = _torch()
+    ij = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=zx.device)
+    rv = torch.empty(max(cap, 1), dtype=torch.float32, device=zx.device)
+    cnt = torch.empty((), dtype=torch.int64, device=zx.device)
+    _check(_lib.pcc_threshold_edges_xy(ctypes.byref(zdx), _dev_ptr(zx, "zx"), ctypes.byref(zdy),
+                                       _dev_ptr(zy, "zy"), float(thr), _dev_ptr(ij, "ij"),
+                                       _dev_ptr(rv, "rv"), cap, _dev_ptr(cnt, "count"),
+                                       ctypes.byref(cfg) if cfg is not None else None, None,
+                                       _stream(torch, stream)), "pcc_threshold_edges_xy")
+    if not sync:
+        return ij, rv, cnt
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    c = int(cnt.item())
+    _check(_lib.pcc_edges_status(c, cap), "pcc_threshold_edges_xy")
+    return ij[:c], rv[:c], c
 
 
 def threshold_edges(z, zd: ZDesc, thr: float, cap: int, cfg: Optional[TileCfg] = None,

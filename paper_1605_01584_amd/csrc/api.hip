@@ -14,9 +14,17 @@ hipError_t launch_normalize(const void *x, int xt, int64_t ldx, const pcc_zdesc 
                             double *stats, int32_t *ndeg, hipStream_t st);
 hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const pcc_tile_cfg &cfg,
                            int grid, hipStream_t st);
+hipError_t launch_allpairs_f64(const pcc_zdesc &zd, const void *z, double *r,
+                               const pcc_tile_cfg &cfg, int grid, hipStream_t st);
 hipError_t launch_edges(const pcc_zdesc &zd, const void *z, float thr, int32_t *ij, float *rv,
                         int64_t cap, int64_t *count, const pcc_tile_cfg &cfg, int grid,
                         hipStream_t st);
+hipError_t launch_allpairs_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &zdy,
+                              const void *zy, float *r, int64_t ldr, const pcc_tile_cfg &cfg,
+                              int grid, hipStream_t st);
+hipError_t launch_edges_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &zdy,
+                           const void *zy, float thr, int32_t *ij, float *rv, int64_t cap,
+                           int64_t *count, const pcc_tile_cfg &cfg, int grid, hipStream_t st);
 hipError_t launch_cells(int64_t m, int diag, int64_t J0, int64_t count, int64_t *y, int64_t *x,
                         hipStream_t st);
 int tile_occupancy(int mode, int tile, int epi);
@@ -27,9 +35,12 @@ int64_t permtest_max_l(int mode);
 namespace {
 
 constexpr int64_t kMaxN = 2147483647LL;  // (i, j) of an edge are int32
-constexpr int64_t kMaxL = 1LL << 22;  // 256 rows of Z stay within 4 GiB (32-bit offsets)
+constexpr int64_t kMaxL = 1LL << 21;  // a 256-row panel of Z stays within 2 GiB (32-bit offsets)
 
-bool valid_mode(int m) { return m >= PCC_FP32 && m <= PCC_FP16; }
+bool valid_mode(int m) { return m >= PCC_FP32 && m <= PCC_FP64; }
+
+// Epilogue kinds of the tile kernels (as in the device core).
+enum { kEpiPacked = 0, kEpiEdges = 1, kEpiRect = 2, kEpiRectEdges = 3, kEpiPackedF64 = 4 };
 
 pcc_status check_zdesc(const pcc_zdesc *zd) {
   if (!zd) return PCC_E_ARG;
@@ -50,6 +61,7 @@ pcc_status check_cfg(const pcc_zdesc &zd, const pcc_tile_cfg *in, pcc_tile_cfg &
     pcc_default_cfg(&zd, &out);
   }
   if (out.tile != 128 && out.tile != 256) return PCC_E_ARG;
+  if (zd.mode == PCC_FP64 && out.tile != 128) return PCC_E_ARG;
   if (out.order != 0 && out.order != 1) return PCC_E_ARG;
   if (out.order == 1 && out.band < 1) return PCC_E_ARG;
   if (out.grid < 0) return PCC_E_ARG;
@@ -65,9 +77,11 @@ int device_cus() {
   return cus;
 }
 
-int grid_for(const pcc_zdesc &zd, const pcc_tile_cfg &cfg, int epi) {
+// Persistent grid: cfg.grid, or compute units x occupancy; never more
+// workgroups than jobs.  ny > 0: the non-symmetric job matrix n x ny.
+int grid_for(const pcc_zdesc &zd, const pcc_tile_cfg &cfg, int epi, int64_t ny = 0) {
   const int64_t m = (zd.n + cfg.tile - 1) / cfg.tile;
-  const int64_t jobs = m * (m + 1) / 2;
+  const int64_t jobs = ny > 0 ? m * ((ny + cfg.tile - 1) / cfg.tile) : m * (m + 1) / 2;
   int64_t g = cfg.grid;
   if (g == 0) {
     const int cus = device_cus();
@@ -108,7 +122,7 @@ int32_t pcc_version(void) { return 10000; }
 pcc_status pcc_z_layout(int64_t n, int64_t l, pcc_mode_t mode, pcc_zdesc *out) {
   if (!out) return PCC_E_ARG;
   if (!valid_mode(mode)) return PCC_E_MODE;
-  if (n < 2 || n > kMaxN || l < 2 || l > kMaxL) return PCC_E_SHAPE;
+  if (n < 1 || n > kMaxN || l < 2 || l > kMaxL) return PCC_E_SHAPE;
   pcc_zdesc d;
   memset(&d, 0, sizeof(d));
   d.n = n;
@@ -130,7 +144,14 @@ pcc_status pcc_default_cfg(const pcc_zdesc *zd, pcc_tile_cfg *out) {
   // in the banded order.  Small ones: 128-wide tiles so that every compute
   // unit gets work.
   const int64_t m256 = (zd->n + 255) / 256;
-  if (m256 * (m256 + 1) / 2 >= 4 * 256) {
+  if (zd->mode == PCC_FP64) {
+    // FP64 tiles are 128 wide; FP64 MFMA is slow enough that 128-wide tiles
+    // already do many flops per staged byte.
+    const int64_t m128 = (zd->n + 127) / 128;
+    c.tile = 128;
+    c.order = 1;
+    c.band = (m128 * (m128 + 1) / 2 >= 4 * 256) ? 8 : 4;
+  } else if (m256 * (m256 + 1) / 2 >= 4 * 256) {
     c.tile = 256;
     c.order = 1;
     c.band = 8;
@@ -165,11 +186,28 @@ pcc_status pcc_allpairs(const pcc_zdesc *zd, const void *z, float *r, const pcc_
   (void)workspace;
   pcc_status s = check_zdesc(zd);
   if (s != PCC_OK) return s;
+  if (zd->n < 2) return PCC_E_SHAPE;  // no pair
   if (!z || !r) return PCC_E_ARG;
   pcc_tile_cfg c;
   s = check_cfg(*zd, cfg, c);
   if (s != PCC_OK) return s;
-  return hip_status(launch_allpairs(*zd, z, r, c, grid_for(*zd, c, 0), (hipStream_t)stream));
+  return hip_status(
+      launch_allpairs(*zd, z, r, c, grid_for(*zd, c, kEpiPacked), (hipStream_t)stream));
+}
+
+pcc_status pcc_allpairs_f64(const pcc_zdesc *zd, const void *z, double *r,
+                            const pcc_tile_cfg *cfg, void *workspace, void *stream) {
+  (void)workspace;
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (zd->n < 2) return PCC_E_SHAPE;  // no pair
+  if (zd->mode != PCC_FP64) return PCC_E_MODE;
+  if (!z || !r) return PCC_E_ARG;
+  pcc_tile_cfg c;
+  s = check_cfg(*zd, cfg, c);
+  if (s != PCC_OK) return s;
+  return hip_status(launch_allpairs_f64(*zd, z, r, c, grid_for(*zd, c, kEpiPackedF64),
+                                        (hipStream_t)stream));
 }
 
 pcc_status pcc_threshold_edges(const pcc_zdesc *zd, const void *z, float thr, int32_t *ij,
@@ -178,13 +216,60 @@ pcc_status pcc_threshold_edges(const pcc_zdesc *zd, const void *z, float thr, in
   (void)workspace;
   pcc_status s = check_zdesc(zd);
   if (s != PCC_OK) return s;
+  if (zd->n < 2) return PCC_E_SHAPE;  // no pair
   if (!z || !count || cap < 0 || (cap > 0 && (!ij || !rv))) return PCC_E_ARG;
   if (!(thr == thr)) return PCC_E_ARG;  // NaN threshold
   pcc_tile_cfg c;
   s = check_cfg(*zd, cfg, c);
   if (s != PCC_OK) return s;
-  return hip_status(
-      launch_edges(*zd, z, thr, ij, rv, cap, count, c, grid_for(*zd, c, 1), (hipStream_t)stream));
+  return hip_status(launch_edges(*zd, z, thr, ij, rv, cap, count, c, grid_for(*zd, c, kEpiEdges),
+                                  (hipStream_t)stream));
+}
+
+// Both operands of a non-symmetric call: valid layouts, same mode and the
+// same samples (so the same row layout).
+static pcc_status check_xy(const pcc_zdesc *zdx, const void *zx, const pcc_zdesc *zdy,
+                           const void *zy) {
+  pcc_status s = check_zdesc(zdx);
+  if (s != PCC_OK) return s;
+  s = check_zdesc(zdy);
+  if (s != PCC_OK) return s;
+  if (zdx->mode != zdy->mode) return PCC_E_MODE;
+  if (zdx->l != zdy->l) return PCC_E_SHAPE;
+  if (!zx || !zy) return PCC_E_ARG;
+  return PCC_OK;
+}
+
+pcc_status pcc_allpairs_xy(const pcc_zdesc *zdx, const void *zx, const pcc_zdesc *zdy,
+                           const void *zy, float *r, int64_t ldr, const pcc_tile_cfg *cfg,
+                           void *workspace, void *stream) {
+  (void)workspace;
+  pcc_status s = check_xy(zdx, zx, zdy, zy);
+  if (s != PCC_OK) return s;
+  if (!r) return PCC_E_ARG;
+  if (ldr < zdy->n) return PCC_E_SHAPE;
+  pcc_tile_cfg c;
+  s = check_cfg(*zdx, cfg, c);
+  if (s != PCC_OK) return s;
+  return hip_status(launch_allpairs_xy(*zdx, zx, *zdy, zy, r, ldr, c,
+                                       grid_for(*zdx, c, kEpiRect, zdy->n), (hipStream_t)stream));
+}
+
+pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx, const pcc_zdesc *zdy,
+                                  const void *zy, float thr, int32_t *ij, float *rv, int64_t cap,
+                                  int64_t *count, const pcc_tile_cfg *cfg, void *workspace,
+                                  void *stream) {
+  (void)workspace;
+  pcc_status s = check_xy(zdx, zx, zdy, zy);
+  if (s != PCC_OK) return s;
+  if (!count || cap < 0 || (cap > 0 && (!ij || !rv))) return PCC_E_ARG;
+  if (!(thr == thr)) return PCC_E_ARG;
+  pcc_tile_cfg c;
+  s = check_cfg(*zdx, cfg, c);
+  if (s != PCC_OK) return s;
+  return hip_status(launch_edges_xy(*zdx, zx, *zdy, zy, thr, ij, rv, cap, count, c,
+                                    grid_for(*zdx, c, kEpiRectEdges, zdy->n),
+                                    (hipStream_t)stream));
 }
 
 pcc_status pcc_edges_status(int64_t count_host, int64_t cap) {
@@ -199,6 +284,7 @@ pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z, const int32_t *perms
   (void)workspace;
   pcc_status s = check_zdesc(zd);
   if (s != PCC_OK) return s;
+  if (zd->n < 2) return PCC_E_SHAPE;  // no pair
   if (!z || !counts || P < 0 || (P > 0 && !perms)) return PCC_E_ARG;
   if (permtest_max_l(zd->mode) <= 0) return PCC_E_MODE;
   if (zd->l_pad > permtest_max_l(zd->mode)) return PCC_E_SHAPE;
@@ -250,6 +336,21 @@ pcc_status pcc_tile_order_host(int64_t m, const pcc_tile_cfg *cfg, int64_t J0, i
   return PCC_OK;
 }
 
+pcc_status pcc_rect_tile_order_host(int64_t mr, int64_t mc, const pcc_tile_cfg *cfg, int64_t J0,
+                                    int64_t count, int64_t *yt, int64_t *xt) {
+  if (!cfg || count < 0 || (count > 0 && (!yt || !xt)) || mr < 1 || mc < 1 || J0 < 0)
+    return PCC_E_ARG;
+  if (cfg->order != 0 && cfg->order != 1) return PCC_E_ARG;
+  if (cfg->order == 1 && cfg->band < 1) return PCC_E_ARG;
+  if (J0 + count > mr * mc) return PCC_E_SHAPE;
+  for (int64_t t = 0; t < count; ++t) {
+    const Cell c = rect_cell(mr, mc, cfg->order, cfg->band, J0 + t);
+    yt[t] = c.y;
+    xt[t] = c.x;
+  }
+  return PCC_OK;
+}
+
 pcc_status pcc_cells_device(int64_t m, int32_t diag, int64_t J0, int64_t count, int64_t *y,
                             int64_t *x, void *stream) {
   if (count < 0 || (count > 0 && (!y || !x)) || m < 1 || J0 < 0) return PCC_E_ARG;
@@ -293,7 +394,7 @@ pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_
       if (times_ms) times_ms[k] = INFINITY;
       continue;
     }
-    const int grid = grid_for(*zd, c, 0);
+    const int grid = grid_for(*zd, c, kEpiPacked);
     std::vector<float> ts;
     for (int rep = 0; rep <= reps && rs == PCC_OK; ++rep) {  // rep 0 warms up
       if (hipEventRecord(e0, st) != hipSuccess || launch_allpairs(*zd, z, r, c, grid, st) != hipSuccess ||

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const Batch
     if (J >= total_jobs) break;  // uniform across the workgroup
     const BatchDesc &d = descs[find_desc(descs, D, J, true)];
     const Cell tc = tri_cell(d.m, J - d.job0);
-    ZView zv{d.z, d.row_bytes, d.n, d.nchunks, d.scale};
+    ZView zv{d.z, d.row_bytes, d.n, d.nchunks, d.scale, d.z, d.n};
     EpiArgs ea{};
     ea.r = d.r;
     if (d.tile == 128)
@@ -165,7 +165,7 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
     pcc_zdesc zd;
     const pcc_status s = pcc_z_layout(it.n, it.l, mode, &zd);
     if (s != PCC_OK) return s;
-    if (it.ldx < it.l) return PCC_E_SHAPE;
+    if (it.n < 2 || it.ldx < it.l) return PCC_E_SHAPE;
     int tile = it.tile;
     if (tile == 0) {
       pcc_tile_cfg c;

@@ -29,7 +29,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Samples per 16-byte output unit.
-template <int MODE> struct UnitOf { static constexpr int E = (MODE == PCC_FP32) ? 4 : 8; };
+template <int MODE> struct UnitOf {
+  static constexpr int E = (MODE == PCC_FP64) ? 2 : ((MODE == PCC_FP32) ? 4 : 8);
+};
 
 // Input samples cached in registers per lane (32: rows up to 2048 samples
 // are read from HBM exactly once).
@@ -39,7 +41,10 @@ template <typename TIn, int E>
 __device__ __forceinline__ void load_unit(const TIn *row, int64_t l, int64_t k0, bool vec,
                                           TIn (&v)[E]) {
   if (vec && k0 + E <= l) {
-    if constexpr (sizeof(TIn) == 4) {
+    if constexpr (sizeof(TIn) == 4 && E == 2) {
+      const float2 f = *reinterpret_cast<const float2 *>(row + k0);
+      v[0] = f.x; v[1] = f.y;
+    } else if constexpr (sizeof(TIn) == 4) {
 #pragma unroll
       for (int q = 0; q < E / 4; ++q) {
         const float4 f = *reinterpret_cast<const float4 *>(row + k0 + 4 * q);
@@ -61,7 +66,9 @@ __device__ __forceinline__ void load_unit(const TIn *row, int64_t l, int64_t k0,
 // Store one unit of E transformed samples (FP64 values) into row `zr`.
 template <int MODE, int E>
 __device__ __forceinline__ void store_unit(unsigned char *zr, int64_t u, const double (&z)[E]) {
-  if constexpr (MODE == PCC_FP32) {
+  if constexpr (MODE == PCC_FP64) {
+    *reinterpret_cast<double2 *>(zr + u * 16) = make_double2(z[0], z[1]);
+  } else if constexpr (MODE == PCC_FP32) {
     float4 o = make_float4((float)z[0], (float)z[1], (float)z[2], (float)z[3]);
     *reinterpret_cast<float4 *>(zr + u * 16) = o;
   } else if constexpr (MODE == PCC_BF16) {

@@ -53,6 +53,7 @@ hipError_t dispatch_mode(const TIn *x, int64_t ldx, const pcc_zdesc &zd, void *z
     case PCC_SPLIT_BF16X3: return launch_norm<TIn, PCC_SPLIT_BF16X3>(x, ldx, zd, z, stats, ndeg, st);
     case PCC_BF16: return launch_norm<TIn, PCC_BF16>(x, ldx, zd, z, stats, ndeg, st);
     case PCC_FP16: return launch_norm<TIn, PCC_FP16>(x, ldx, zd, z, stats, ndeg, st);
+    case PCC_FP64: return launch_norm<TIn, PCC_FP64>(x, ldx, zd, z, stats, ndeg, st);
   }
   return hipErrorInvalidValue;
 }

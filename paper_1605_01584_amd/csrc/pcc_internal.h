@@ -82,6 +82,18 @@ PCC_HD Cell tile_of_job(int64_t m, int order, int64_t H, int64_t J) {
   return (order == 1 && H > 1) ? band_cell(m, H, J) : tri_cell(m, J);
 }
 
+// Non-symmetric all-pairs over an mr x mc tile rectangle, Eq. (7)-(8): every
+// cell is a job, J = y mc + x, x = J % mc, y = J / mc.  Banded order: bands
+// of H tile rows, band b = [bH, bH + h) with h = min(H, mr - bH), starts at
+// id bH mc and is walked column by column, top to bottom.
+PCC_HD Cell rect_cell(int64_t mr, int64_t mc, int order, int64_t H, int64_t J) {
+  if (order != 1 || H <= 1) return Cell{J / mc, J % mc};
+  const int64_t r0 = (J / mc) / H * H;
+  const int64_t h = (mr - r0) < H ? (mr - r0) : H;
+  const int64_t o = J - r0 * mc;
+  return Cell{r0 + o % h, o / h};
+}
+
 // ---------------------------------------------------------------------------
 // Number formats.
 
@@ -100,26 +112,9 @@ PCC_HD float bf16_bits_to_f32(uint16_t h) {
 constexpr int kChunkBytes = 128;
 constexpr int kRowPadMultiple = 256;
 
-inline int kchunk_of(int mode) { return (mode == PCC_FP32 || mode == PCC_SPLIT_BF16X3) ? 32 : 64; }
-
-// Kernel launch parameters of the tile kernels.
-struct TileArgs {
-  const unsigned char *z;  // Z base
-  int64_t row_bytes;
-  int64_t n;               // profiles
-  int64_t m;               // tiles per side
-  int64_t njobs;           // m(m+1)/2
-  int32_t nchunks;         // l_pad / kchunk
-  int32_t order;
-  int32_t band;
-  float scale;             // multiply accumulators by this (FP16: 1/l)
-  // outputs
-  float *r;                // packed triangle (allpairs)
-  float thr;               // edges
-  int32_t *ij;
-  float *rv;
-  int64_t cap;
-  unsigned long long *count;
-};
+inline int kchunk_of(int mode) {
+  if (mode == PCC_FP64) return 16;
+  return (mode == PCC_FP32 || mode == PCC_SPLIT_BF16X3) ? 32 : 64;
+}
 
 }  // namespace pcc

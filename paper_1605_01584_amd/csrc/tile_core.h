@@ -29,6 +29,15 @@
 //   SPLIT  half h: hi unit 2h+g and lo unit 4+2h+g of the same 8 samples;
 //          three 32x32x16 MFMAs lo.hi + hi.lo + hi.hi into one FP32
 //          accumulator (the lo.lo term, about 2^-16 of r, is dropped).
+//   FP64   (do_tile_f64, 128-wide tiles, 16 x 16 blocks) lane (j, g4),
+//          j = lane % 16, g4 = lane / 16, reads units g4 and g4 + 4 of row j
+//          (4 doubles); k-step (h, e) takes double e of unit g4 + 4h, i.e.
+//          sample 8h + 2g4 + e, as its k index g4.
+//
+// The same core serves the symmetric job matrix (column operand = row
+// operand, strict upper triangle kept, Eq. (5)) and the non-symmetric one of
+// two variable sets (Eq. (7)-(8), every cell kept); the epilogue kind EPI
+// selects the mask and where r goes.
 #pragma once
 
 #include "pcc_internal.h"
@@ -40,25 +49,41 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-enum { EPI_PACKED = 0, EPI_EDGES = 1 };
+// Epilogue kinds:
+//   EPI_PACKED      symmetric, packed strict upper triangle, FP32 r
+//   EPI_EDGES       symmetric, |r| >= thr appended to an edge list
+//   EPI_RECT        non-symmetric, r[y * ldr + x], FP32
+//   EPI_RECT_EDGES  non-symmetric edge list
+//   EPI_PACKED_F64  symmetric, packed, FP64 r (FP64 mode only)
+enum { EPI_PACKED = 0, EPI_EDGES = 1, EPI_RECT = 2, EPI_RECT_EDGES = 3, EPI_PACKED_F64 = 4 };
 
 constexpr int kTileThreads = 512;  // 8 waves
+// num_records of the panel buffer descriptors: 2^32 - 1 bytes.  A panel is at
+// most 256 rows of at most 2^21 samples x 4 bytes (or 128 rows x 8 bytes),
+// 2 GiB, so every load of a tile lies inside it and its 32-bit offset.
+constexpr int kPanelRange = (int)0xffffffffu;
 constexpr int kWavesR = 4, kWavesC = 2;
 
-// Z operand of one tile computation.
+// Z operands of one tile computation.
 struct ZView {
-  const unsigned char *z;
-  int64_t row_bytes;
-  int64_t n;
+  const unsigned char *z;   // row operand (profiles y)
+  int64_t row_bytes;        // both operands
+  int64_t n;                // profiles of the row operand
   int32_t nchunks;
-  float scale;  // accumulator -> r (FP16 layout: 1/l)
+  float scale;              // accumulator -> r (FP16 layout: 1/l)
+  const unsigned char *zc;  // column operand (profiles x); == z when symmetric
+  int64_t nc;               // profiles of the column operand
 };
 
 // Output of one tile computation.
 struct EpiArgs {
-  float *r;                 // packed strict upper triangle
+  float *r;                 // packed triangle, or nx x ldr rectangle
+  double *r64;              // packed triangle in FP64
+  int64_t ldr;              // rectangle row pitch
   float thr;                // edges: |r| >= thr
   int32_t *ij;
   float *rv;
@@ -80,6 +105,49 @@ __device__ __forceinline__ float clamp_unit(float r) {
   // NaN passes through (both comparisons false).
   return r > 1.0f ? 1.0f : (r < -1.0f ? -1.0f : r);
 }
+
+__device__ __forceinline__ double clamp_unit(double r) {
+  return r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
+}
+
+// Mask, output row base and store of one r value for epilogue kind EPI.
+template <int EPI> struct Epi {
+  static constexpr bool kRect = EPI == EPI_RECT || EPI == EPI_RECT_EDGES;
+  static constexpr bool kEdges = EPI == EPI_EDGES || EPI == EPI_RECT_EDGES;
+  // Packed: row y of the strict upper triangle starts at F_{n-1}(y) - y - 1 + x.
+  static __device__ __forceinline__ int64_t rowbase(const ZView &zv, const EpiArgs &ea,
+                                                    int64_t y) {
+    if constexpr (kRect)
+      return y * ea.ldr;
+    else
+      return tri_F(zv.n - 1, y) - 1 - y;
+  }
+  static __device__ __forceinline__ bool keep(const ZView &zv, int64_t y, int64_t x) {
+    if constexpr (kRect)
+      return y < zv.n && x < zv.nc;
+    else
+      return y < x && x < zv.n;
+  }
+  // rv is already clamped (NaN kept: it fails |rv| >= thr).
+  template <typename T>
+  static __device__ __forceinline__ void emit(const EpiArgs &ea, int64_t rb, int64_t y, int64_t x,
+                                              T rv) {
+    if constexpr (EPI == EPI_PACKED_F64) {
+      __builtin_nontemporal_store((double)rv, ea.r64 + rb + x);
+    } else if constexpr (kEdges) {
+      if ((rv < (T)0 ? -rv : rv) >= (T)ea.thr) {
+        const unsigned long long s = atomicAdd(ea.count, 1ull);
+        if ((int64_t)s < ea.cap) {
+          ea.ij[2 * s] = (int32_t)y;
+          ea.ij[2 * s + 1] = (int32_t)x;
+          ea.rv[s] = (float)rv;
+        }
+      }
+    } else {
+      __builtin_nontemporal_store((float)rv, ea.r + rb + x);
+    }
+  }
+};
 
 __device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
   // Workgroups are dispatched to the 8 XCDs round robin (b % 8); give the
@@ -196,11 +264,11 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
   const int i = lane & 31, g = lane >> 5;
   const int64_t rb = zv.row_bytes;
   const unsigned char *za = zv.z + yt * TILE * rb;
-  const unsigned char *zb = zv.z + xt * TILE * rb;
+  const unsigned char *zb = zv.zc + xt * TILE * rb;
   const __amdgpu_buffer_rsrc_t rsa =
-      __builtin_amdgcn_make_buffer_rsrc((void *)za, (short)0, 0x7fffffff, 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc((void *)za, (short)0, kPanelRange, 0x00020000);
   const __amdgpu_buffer_rsrc_t rsb =
-      __builtin_amdgcn_make_buffer_rsrc((void *)zb, (short)0, 0x7fffffff, 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc((void *)zb, (short)0, kPanelRange, 0x00020000);
   const int ro = lane >> 3;
   const uint32_t lane_row_off = (uint32_t)((8 * IPW * w + ro) * rb);
   const uint32_t uoff_even = (uint32_t)(((lane & 7) ^ lds_swz(ro)) * 16);
@@ -250,9 +318,7 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
   }
 
   // Epilogue.  Lane holds column x0 + 32q + i of block (p, q); accumulator
-  // register v holds row 8*(v/4) + 4*g + (v%4) of the block.  Row y of the
-  // packed triangle starts at F_{n-1}(y) - y - 1 + x.
-  const int64_t n = zv.n;
+  // register v holds row 8*(v/4) + 4*g + (v%4) of the block.
   const int64_t y0 = yt * TILE + wr * WTR;
   const int64_t x0 = xt * TILE + wc * WTC;
 #pragma unroll
@@ -260,25 +326,140 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-      const int64_t rowbase = tri_F(n - 1, y) - 1 - y;
+      const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
 #pragma unroll
       for (int q = 0; q < NBC; ++q) {
         const int64_t x = x0 + q * 32 + i;
-        if (y < x && x < n) {
-          const float rv = clamp_unit(acc[p][q][v] * zv.scale);
-          if constexpr (EPI == EPI_PACKED) {
-            __builtin_nontemporal_store(rv, ea.r + rowbase + x);
-          } else {
-            if (fabsf(rv) >= ea.thr) {
-              const unsigned long long s = atomicAdd(ea.count, 1ull);
-              if ((int64_t)s < ea.cap) {
-                ea.ij[2 * s] = (int32_t)y;
-                ea.ij[2 * s + 1] = (int32_t)x;
-                ea.rv[s] = rv;
-              }
-            }
-          }
-        }
+        if (Epi<EPI>::keep(zv, y, x))
+          Epi<EPI>::emit(ea, rbase, y, x, clamp_unit(acc[p][q][v] * zv.scale));
+      }
+    }
+  }
+}
+
+// FP64 tile (yt, xt), 128 x 128, same workgroup shape, LDS stages and DMA as
+// do_tile; each wave owns 32 x 64 = 2 x 4 blocks of 16 x 16 FP64
+// accumulators (v_mfma_f64_16x16x4_f64).  One FP64 MFMA is long, so whole
+// stages are pipelined: stage c + 1's fragments are read (after the stage
+// barrier) before stage c's 32 MFMAs are issued.
+template <int EPI>
+__device__ __forceinline__ void do_tile_f64(const ZView &zv, const EpiArgs &ea, int64_t yt,
+                                            int64_t xt, u32x4 *__restrict__ smem) {
+  constexpr int TILE = 128;
+  using S = TileShape<TILE>;
+  constexpr int WTR = S::WTR, WTC = S::WTC, OPU = S::OPU, IPW = S::IPW;
+  constexpr int FR = WTR / 16, FC = WTC / 16;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = w / kWavesC, wc = w % kWavesC;
+  const int j = lane & 15, g4 = lane >> 4;
+  const int64_t rb = zv.row_bytes;
+  const unsigned char *za = zv.z + yt * TILE * rb;
+  const unsigned char *zb = zv.zc + xt * TILE * rb;
+  const __amdgpu_buffer_rsrc_t rsa =
+      __builtin_amdgcn_make_buffer_rsrc((void *)za, (short)0, kPanelRange, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsb =
+      __builtin_amdgcn_make_buffer_rsrc((void *)zb, (short)0, kPanelRange, 0x00020000);
+  const int ro = lane >> 3;
+  const uint32_t lane_row_off = (uint32_t)((8 * IPW * w + ro) * rb);
+  const uint32_t uoff_even = (uint32_t)(((lane & 7) ^ lds_swz(ro)) * 16);
+  const uint32_t uoff_odd = (uint32_t)(((lane & 7) ^ lds_swz(ro + 8)) * 16);
+  const uint32_t row8 = (uint32_t)(8 * rb);
+  const int nch = zv.nchunks;
+  // rows 16p + j of a wave's band sit at row offsets that are multiples of
+  // 16 plus j, so their swizzle is lds_swz(j)
+  const int sw = lds_swz(j);
+  const int aoff = (wr * WTR + j) * 8, boff = OPU + (wc * WTC + j) * 8;
+  const int u0 = g4 ^ sw, u1 = (g4 + 4) ^ sw;
+
+  f64x4 acc[FR][FC];
+#pragma unroll
+  for (int p = 0; p < FR; ++p)
+#pragma unroll
+    for (int q = 0; q < FC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[p][q][v] = 0.0;
+
+  u32x4 ca[2][FR], cb[2][FC], na[2][FR], nb[2][FC];
+  __syncthreads();  // every wave is done reading the previous tile's stages
+  dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8, 0u, smem, w);
+  if (nch > 1) {
+    dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8, 128u, smem + 2 * OPU, w);
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * IPW) : "memory");  // stage 0 landed
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < FR; ++p) {
+    ca[0][p] = smem[aoff + p * 128 + u0];
+    ca[1][p] = smem[aoff + p * 128 + u1];
+  }
+#pragma unroll
+  for (int q = 0; q < FC; ++q) {
+    cb[0][q] = smem[boff + q * 128 + u0];
+    cb[1][q] = smem[boff + q * 128 + u1];
+  }
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) {
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+      __syncthreads();  // stage c + 1 landed everywhere; stage c's buffer is free
+      const u32x4 *nxt = smem + ((c + 1) & 1) * 2 * OPU;
+#pragma unroll
+      for (int p = 0; p < FR; ++p) {
+        na[0][p] = nxt[aoff + p * 128 + u0];
+        na[1][p] = nxt[aoff + p * 128 + u1];
+      }
+#pragma unroll
+      for (int q = 0; q < FC; ++q) {
+        nb[0][q] = nxt[boff + q * 128 + u0];
+        nb[1][q] = nxt[boff + q * 128 + u1];
+      }
+      if (c + 2 < nch)
+        dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8,
+                        (uint32_t)(c + 2) * 128u, smem + (c & 1) * 2 * OPU, w);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f64x2 a[FR], b[FC];
+#pragma unroll
+      for (int p = 0; p < FR; ++p) a[p] = __builtin_bit_cast(f64x2, ca[h][p]);
+#pragma unroll
+      for (int q = 0; q < FC; ++q) b[q] = __builtin_bit_cast(f64x2, cb[h][q]);
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int p = 0; p < FR; ++p)
+#pragma unroll
+          for (int q = 0; q < FC; ++q)
+            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p][e], b[q][e], acc[p][q], 0, 0, 0);
+    }
+    if (c + 1 < nch) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int p = 0; p < FR; ++p) ca[h][p] = na[h][p];
+#pragma unroll
+        for (int q = 0; q < FC; ++q) cb[h][q] = nb[h][q];
+      }
+    }
+  }
+
+  // Epilogue.  Lane (j, g4) holds column 16q + j of block (p, q); its
+  // accumulator element v is row g4 + 4v (the FP64 form interleaves rows
+  // across the four lane groups, unlike the FP32 16 x 16 forms).
+  const int64_t y0 = yt * TILE + wr * WTR;
+  const int64_t x0 = xt * TILE + wc * WTC;
+#pragma unroll
+  for (int p = 0; p < FR; ++p) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t y = y0 + p * 16 + g4 + 4 * v;
+      const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+#pragma unroll
+      for (int q = 0; q < FC; ++q) {
+        const int64_t x = x0 + q * 16 + j;
+        if (Epi<EPI>::keep(zv, y, x)) Epi<EPI>::emit(ea, rbase, y, x, clamp_unit(acc[p][q][v]));
       }
     }
   }

@@ -1,6 +1,11 @@
-// Uniform all-pairs kernels: Eq. (5) evaluated on the upper-triangle tiles
-// only (Sec. III-C), every tile placed from its tile id by the bijection of
+// Uniform all-pairs kernels.
+//
+// Symmetric job matrix: Eq. (5) evaluated on the upper-triangle tiles only
+// (Sec. III-C), every tile placed from its tile id by the bijection of
 // Eq. (16)-(19) (or the banded order built on it).
+// Non-symmetric job matrix (two variable sets): every tile of the
+// mr x mc tile rectangle is a job, placed by Eq. (7)-(8) (or bands of tile
+// rows walked column by column).
 //
 // Persistent grid (the static stride of the multithreaded tile kernel over
 // tile ids): workgroup b takes ids s(b), s(b) + G, s(b) + 2G, ..., where s()
@@ -14,39 +19,61 @@ namespace {
 struct UniformArgs {
   ZView zv;
   EpiArgs ea;
-  int64_t m;      // tiles per side
-  int64_t njobs;  // m(m+1)/2
+  int64_t mr;     // tile rows
+  int64_t mc;     // tile columns (non-symmetric)
+  int64_t njobs;  // mr(mr+1)/2 or mr mc
   int32_t order;
   int32_t band;
 };
+
+template <int EPI> constexpr bool is_rect() { return EPI == EPI_RECT || EPI == EPI_RECT_EDGES; }
 
 template <int MODE, int TILE, int EPI>
 __global__ __launch_bounds__(kTileThreads, 1) void tile_kernel(UniformArgs a) {
   __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
   const int64_t G = gridDim.x;
   for (int64_t J = xcd_slot(blockIdx.x, G); J < a.njobs; J += G) {
-    const Cell tc = tile_of_job(a.m, a.order, a.band, J);
-    do_tile<MODE, TILE, EPI>(a.zv, a.ea, tc.y, tc.x, smem);
+    Cell tc;
+    if constexpr (is_rect<EPI>())
+      tc = rect_cell(a.mr, a.mc, a.order, a.band, J);
+    else
+      tc = tile_of_job(a.mr, a.order, a.band, J);
+    if constexpr (MODE == PCC_FP64)
+      do_tile_f64<EPI>(a.zv, a.ea, tc.y, tc.x, smem);
+    else
+      do_tile<MODE, TILE, EPI>(a.zv, a.ea, tc.y, tc.x, smem);
   }
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
 
 template <int MODE, int EPI> const void *kernel_ptr_t(int tile) {
-  return tile == 128 ? (const void *)tile_kernel<MODE, 128, EPI>
-                     : (const void *)tile_kernel<MODE, 256, EPI>;
+  if constexpr (MODE == PCC_FP64)
+    return tile == 128 ? (const void *)tile_kernel<MODE, 128, EPI> : nullptr;
+  else
+    return tile == 128 ? (const void *)tile_kernel<MODE, 128, EPI>
+                       : (const void *)tile_kernel<MODE, 256, EPI>;
+}
+
+template <int EPI> const void *kernel_for_epi(int mode, int tile) {
+  switch (mode) {
+    case PCC_FP32: return kernel_ptr_t<PCC_FP32, EPI>(tile);
+    case PCC_SPLIT_BF16X3: return kernel_ptr_t<PCC_SPLIT_BF16X3, EPI>(tile);
+    case PCC_BF16: return kernel_ptr_t<PCC_BF16, EPI>(tile);
+    case PCC_FP16: return kernel_ptr_t<PCC_FP16, EPI>(tile);
+    case PCC_FP64: return kernel_ptr_t<PCC_FP64, EPI>(tile);
+  }
+  return nullptr;
 }
 
 const void *kernel_for(int mode, int tile, int epi) {
-  switch (mode) {
-    case PCC_FP32:
-      return epi ? kernel_ptr_t<PCC_FP32, 1>(tile) : kernel_ptr_t<PCC_FP32, 0>(tile);
-    case PCC_SPLIT_BF16X3:
-      return epi ? kernel_ptr_t<PCC_SPLIT_BF16X3, 1>(tile) : kernel_ptr_t<PCC_SPLIT_BF16X3, 0>(tile);
-    case PCC_BF16:
-      return epi ? kernel_ptr_t<PCC_BF16, 1>(tile) : kernel_ptr_t<PCC_BF16, 0>(tile);
-    case PCC_FP16:
-      return epi ? kernel_ptr_t<PCC_FP16, 1>(tile) : kernel_ptr_t<PCC_FP16, 0>(tile);
+  switch (epi) {
+    case EPI_PACKED: return kernel_for_epi<EPI_PACKED>(mode, tile);
+    case EPI_EDGES: return kernel_for_epi<EPI_EDGES>(mode, tile);
+    case EPI_RECT: return kernel_for_epi<EPI_RECT>(mode, tile);
+    case EPI_RECT_EDGES: return kernel_for_epi<EPI_RECT_EDGES>(mode, tile);
+    case EPI_PACKED_F64:
+      return mode == PCC_FP64 ? kernel_ptr_t<PCC_FP64, EPI_PACKED_F64>(tile) : nullptr;
   }
   return nullptr;
 }
@@ -67,31 +94,50 @@ UniformArgs make_args(const pcc_zdesc &zd, const void *z, const pcc_tile_cfg &cf
   a.zv.n = zd.n;
   a.zv.nchunks = (int32_t)(zd.l_pad / zd.kchunk);
   a.zv.scale = (zd.mode == PCC_FP16) ? (float)(1.0 / (double)zd.l) : 1.0f;
-  a.m = (zd.n + cfg.tile - 1) / cfg.tile;
-  a.njobs = a.m * (a.m + 1) / 2;
+  a.zv.zc = a.zv.z;
+  a.zv.nc = zd.n;
+  a.mr = (zd.n + cfg.tile - 1) / cfg.tile;
+  a.mc = a.mr;
+  a.njobs = a.mr * (a.mr + 1) / 2;
   a.order = cfg.order;
   a.band = cfg.band;
   return a;
 }
 
-hipError_t launch(const pcc_zdesc &zd, UniformArgs a, int tile, int epi, int grid,
-                  hipStream_t st) {
-  const void *k = kernel_for(zd.mode, tile, epi);
+UniformArgs make_args_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &zdy,
+                         const void *zy, const pcc_tile_cfg &cfg) {
+  UniformArgs a = make_args(zdx, zx, cfg);
+  a.zv.zc = (const unsigned char *)zy;
+  a.zv.nc = zdy.n;
+  a.mc = (zdy.n + cfg.tile - 1) / cfg.tile;
+  a.njobs = a.mr * a.mc;
+  return a;
+}
+
+hipError_t launch(int mode, UniformArgs a, int tile, int epi, int grid, hipStream_t st) {
+  const void *k = kernel_for(mode, tile, epi);
   if (!k) return hipErrorInvalidValue;
+  if (grid < 1) grid = 1;
+  if (a.njobs < grid) grid = (int)a.njobs;
   void *args[] = {(void *)&a};
   return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, st);
+}
+
+hipError_t zero_count(int64_t *count, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, (unsigned long long *)count);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 int tile_occupancy(int mode, int tile, int epi) {
-  static int cache[4][2][2] = {};
-  if (mode < 0 || mode > 3) return 1;
-  int &c = cache[mode][tile == 128 ? 0 : 1][epi ? 1 : 0];
+  static int cache[5][2][5] = {};
+  if (mode < 0 || mode > 4 || epi < 0 || epi > 4) return 1;
+  int &c = cache[mode][tile == 128 ? 0 : 1][epi];
   if (c == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_for(mode, tile, epi), kTileThreads, 0) !=
-            hipSuccess ||
+    const void *k = kernel_for(mode, tile, epi);
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTileThreads, 0) != hipSuccess ||
         nb < 1)
       nb = 1;
     c = nb;
@@ -103,14 +149,20 @@ hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const p
                            int grid, hipStream_t st) {
   UniformArgs a = make_args(zd, z, cfg);
   a.ea.r = r;
-  return launch(zd, a, cfg.tile, EPI_PACKED, grid, st);
+  return launch(zd.mode, a, cfg.tile, EPI_PACKED, grid, st);
+}
+
+hipError_t launch_allpairs_f64(const pcc_zdesc &zd, const void *z, double *r,
+                               const pcc_tile_cfg &cfg, int grid, hipStream_t st) {
+  UniformArgs a = make_args(zd, z, cfg);
+  a.ea.r64 = r;
+  return launch(zd.mode, a, cfg.tile, EPI_PACKED_F64, grid, st);
 }
 
 hipError_t launch_edges(const pcc_zdesc &zd, const void *z, float thr, int32_t *ij, float *rv,
                         int64_t cap, int64_t *count, const pcc_tile_cfg &cfg, int grid,
                         hipStream_t st) {
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, (unsigned long long *)count);
-  hipError_t e = hipGetLastError();
+  hipError_t e = zero_count(count, st);
   if (e != hipSuccess) return e;
   UniformArgs a = make_args(zd, z, cfg);
   a.ea.thr = thr;
@@ -118,7 +170,30 @@ hipError_t launch_edges(const pcc_zdesc &zd, const void *z, float thr, int32_t *
   a.ea.rv = rv;
   a.ea.cap = cap;
   a.ea.count = (unsigned long long *)count;
-  return launch(zd, a, cfg.tile, EPI_EDGES, grid, st);
+  return launch(zd.mode, a, cfg.tile, EPI_EDGES, grid, st);
+}
+
+hipError_t launch_allpairs_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &zdy,
+                              const void *zy, float *r, int64_t ldr, const pcc_tile_cfg &cfg,
+                              int grid, hipStream_t st) {
+  UniformArgs a = make_args_xy(zdx, zx, zdy, zy, cfg);
+  a.ea.r = r;
+  a.ea.ldr = ldr;
+  return launch(zdx.mode, a, cfg.tile, EPI_RECT, grid, st);
+}
+
+hipError_t launch_edges_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &zdy,
+                           const void *zy, float thr, int32_t *ij, float *rv, int64_t cap,
+                           int64_t *count, const pcc_tile_cfg &cfg, int grid, hipStream_t st) {
+  hipError_t e = zero_count(count, st);
+  if (e != hipSuccess) return e;
+  UniformArgs a = make_args_xy(zdx, zx, zdy, zy, cfg);
+  a.ea.thr = thr;
+  a.ea.ij = ij;
+  a.ea.rv = rv;
+  a.ea.cap = cap;
+  a.ea.count = (unsigned long long *)count;
+  return launch(zdx.mode, a, cfg.tile, EPI_RECT_EDGES, grid, st);
 }
 
 hipError_t launch_cells(int64_t m, int diag, int64_t J0, int64_t count, int64_t *y, int64_t *x,

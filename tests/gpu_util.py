@@ -27,6 +27,8 @@ def decode_z(zbytes: np.ndarray, zd) -> dict:
     if mode == 0:  # FP32
         v = raw.view(np.float32).astype(np.float64)
         return {"value": v}
+    if mode == 4:  # FP64
+        return {"value": raw.view(np.float64).copy()}
     if mode == 2:  # BF16
         v = bf16_to_f32(raw.view(np.uint16)).astype(np.float64)
         return {"value": v}

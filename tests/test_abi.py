@@ -34,7 +34,7 @@ def test_status_strings_and_version():
 
 
 @pytest.mark.parametrize("mode,kchunk,elem", [("fp32", 32, 4), ("split", 32, 4), ("bf16", 64, 2),
-                                              ("fp16", 64, 2)])
+                                              ("fp16", 64, 2), ("fp64", 16, 8)])
 @pytest.mark.parametrize("n,l", [(2, 2), (2000, 256), (257, 65), (32768, 4096), (65536, 2048)])
 def test_layout(mode, kchunk, elem, n, l):
     import paper_1605_01584_amd as pcc
@@ -48,10 +48,22 @@ def test_layout(mode, kchunk, elem, n, l):
 
 def test_layout_rejects():
     import paper_1605_01584_amd as pcc
-    for n, l in [(1, 10), (0, 10), (10, 1), (10, 0), (2 ** 31, 10), (10, 2 ** 22 + 1)]:
+    for n, l in [(0, 10), (-1, 10), (10, 1), (10, 0), (2 ** 31, 10), (10, 2 ** 21 + 1)]:
         with pytest.raises(pcc.PccError) as e:
             pcc.z_layout(n, l)
         assert e.value.status == pcc.PCC_E_SHAPE
+    # one profile is a valid layout (a query against a set), but not a pair set
+    one = pcc.z_layout(1, 10)
+    fake = ctypes.c_void_p(0x1000)
+    assert pcc._lib.pcc_allpairs(ctypes.byref(one), fake, fake, None, None, None) == pcc.PCC_E_SHAPE
+    assert pcc._lib.pcc_threshold_edges(ctypes.byref(one), fake, 0.5, fake, fake, 1, fake, None,
+                                        None, None) == pcc.PCC_E_SHAPE
+    assert pcc._lib.pcc_permtest(ctypes.byref(one), fake, fake, 1, fake, None, None) == pcc.PCC_E_SHAPE
+    # the largest accepted l keeps a 256-row panel within 2 GiB (32-bit loads)
+    for mode in ("fp32", "split", "bf16", "fp16", "fp64"):
+        zd = pcc.z_layout(10, 2 ** 21, mode)
+        tile = 128 if mode == "fp64" else 256
+        assert tile * zd.row_bytes <= 2 ** 31
     with pytest.raises(pcc.PccError) as e:
         pcc.z_layout(10, 10, 7)
     assert e.value.status == pcc.PCC_E_MODE
@@ -141,3 +153,53 @@ def test_permtest_limit_is_lds_bound():
     lim = pcc.permtest_max_l("fp32")
     assert lim > 0 and lim % 32 == 0
     assert pcc.permtest_max_l("bf16") == 0
+
+
+def test_fp64_and_xy_argument_errors():
+    import paper_1605_01584_amd as pcc
+    lib = pcc._lib
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    z64 = pcc.z_layout(100, 50, "fp64")
+    z32 = pcc.z_layout(100, 50, "fp32")
+    # FP64 tiles are 128 wide only; the FP64-output entry point needs FP64 Z
+    c256 = pcc.TileCfg(256, 0, 1, 0)
+    assert lib.pcc_allpairs(ctypes.byref(z64), fake, fake, ctypes.byref(c256), None,
+                            None) == pcc.PCC_E_ARG
+    assert lib.pcc_allpairs_f64(ctypes.byref(z32), fake, fake, None, None, None) == pcc.PCC_E_MODE
+    assert lib.pcc_allpairs_f64(ctypes.byref(z64), fake, None, None, None, None) == pcc.PCC_E_ARG
+    assert pcc.default_cfg(z64).tile == 128
+    assert pcc.default_cfg(pcc.z_layout(40000, 300, "fp64")).tile == 128
+    # FP64 is not a permutation-test or batch mode
+    assert lib.pcc_permtest(ctypes.byref(z64), fake, fake, 3, fake, None, None) == pcc.PCC_E_MODE
+    plan = ctypes.c_void_p()
+    items = (pcc.BatchItem * 1)()
+    items[0] = pcc.BatchItem(0x1000, 50, 100, 50, 0, 0, 0x1000, 0x1000)
+    assert lib.pcc_batch_plan_create(1, items, pcc.FP64, fake, 1 << 20, None,
+                                     ctypes.byref(plan)) == pcc.PCC_E_MODE
+    # non-symmetric: same mode and samples, output pitch >= ny, pointers
+    zy = pcc.z_layout(70, 50, "fp32")
+    zy_l = pcc.z_layout(70, 51, "fp32")
+    zy_m = pcc.z_layout(70, 50, "split")
+    xy = lib.pcc_allpairs_xy
+    assert xy(ctypes.byref(z32), fake, ctypes.byref(zy_m), fake, fake, 70, None, None,
+              None) == pcc.PCC_E_MODE
+    assert xy(ctypes.byref(z32), fake, ctypes.byref(zy_l), fake, fake, 70, None, None,
+              None) == pcc.PCC_E_SHAPE
+    assert xy(ctypes.byref(z32), fake, ctypes.byref(zy), fake, fake, 69, None, None,
+              None) == pcc.PCC_E_SHAPE
+    assert xy(ctypes.byref(z32), fake, ctypes.byref(zy), None, fake, 70, None, None,
+              None) == pcc.PCC_E_ARG
+    assert xy(ctypes.byref(z32), fake, ctypes.byref(zy), fake, None, 70, None, None,
+              None) == pcc.PCC_E_ARG
+    assert xy(ctypes.byref(z32), fake, None, fake, fake, 70, None, None, None) == pcc.PCC_E_ARG
+    ex = lib.pcc_threshold_edges_xy
+    assert ex(ctypes.byref(z32), fake, ctypes.byref(zy), fake, float("nan"), fake, fake, 10, fake,
+              None, None, None) == pcc.PCC_E_ARG
+    assert ex(ctypes.byref(z32), fake, ctypes.byref(zy), fake, 0.5, fake, fake, 10, None,
+              None, None, None) == pcc.PCC_E_ARG
+    assert ex(ctypes.byref(z32), fake, ctypes.byref(zy_m), fake, 0.5, fake, fake, 10, fake,
+              None, None, None) == pcc.PCC_E_MODE
+    # rectangle order helper
+    cfg = pcc.TileCfg(128, 1, 4, 0)
+    assert lib.pcc_rect_tile_order_host(3, 4, ctypes.byref(cfg), 10, 5, fake, fake) == pcc.PCC_E_SHAPE
+    assert lib.pcc_rect_tile_order_host(0, 4, ctypes.byref(cfg), 0, 1, fake, fake) == pcc.PCC_E_ARG

@@ -9,7 +9,7 @@ from gpu_util import decode_z, to_device
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["fp32", "split", "bf16", "fp16"]
+MODES = ["fp32", "split", "bf16", "fp16", "fp64"]
 
 
 def _run(X, mode, dtype=None, stats=True, ld=None):
@@ -25,7 +25,8 @@ def _run(X, mode, dtype=None, stats=True, ld=None):
     return z.cpu().numpy(), zd, st.cpu().numpy(), int(nd.item())
 
 
-def _check_values(Z, zd, U, mode):
+def _check_values(Z, zd, U, mode, scale=None):
+    """scale (FP64 mode): max|x| / sqrt(M2) of every row."""
     n, l = U.shape
     dec = decode_z(Z, zd)
     V = dec["value"]
@@ -33,7 +34,15 @@ def _check_values(Z, zd, U, mode):
     assert np.all(V[:, l:] == 0.0), "padding samples must be zero"
     A = np.abs(U)
     d = np.abs(V[:n, :l] - U)
-    if mode == "fp32":
+    if mode == "fp64":
+        # no rounding to a narrower format: a few FP64 roundings (deviation,
+        # sqrt, reciprocal, product) on each side, 16 ulp relative; and both
+        # sides sum the mean, in different orders, each within l ulp of
+        # max|x|, which shifts z by at most 2 l 2^-53 max|x| / sqrt(M2)
+        assert scale is not None
+        atol = 2.0 * l * 2.0 ** -53 * scale[:, None]
+        assert np.all(d <= 16 * 2.0 ** -53 * A + atol)
+    elif mode == "fp32":
         assert np.all(d <= 2.0 ** -24 * A + 1e-14)
     elif mode == "bf16":
         assert np.all(d <= (2.0 ** -8 + 2.0 ** -24) * A + 1e-14)
@@ -55,7 +64,7 @@ def test_config1_fp64_input(mode):
     assert nd == 0
     np.testing.assert_allclose(st[:, 0], mean, rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(st[:, 1], m2, rtol=1e-12)
-    _check_values(Z, zd, U, mode)
+    _check_values(Z, zd, U, mode, np.abs(X).max(axis=1) / np.sqrt(m2))
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -68,7 +77,7 @@ def test_ragged_lengths_fp32_input(mode, l):
     assert nd == 0
     np.testing.assert_allclose(st[:, 0], mean, rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(st[:, 1], m2, rtol=1e-12)
-    _check_values(Z, zd, U, mode)
+    _check_values(Z, zd, U, mode, np.abs(X.astype(np.float64)).max(axis=1) / np.sqrt(m2))
 
 
 @pytest.mark.parametrize("ld", [101, 104, 128])

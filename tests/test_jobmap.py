@@ -111,3 +111,41 @@ def test_paper_order_matches_enumeration():
     y, x = pcc.tile_order_host(m, pcc.TileCfg(256, 0, 1, 0), 0, m * (m + 1) // 2)
     ys, xs = oracle.enumerate_upper(m, True)
     assert np.array_equal(y, ys) and np.array_equal(x, xs)
+
+
+def _rect_row_major(mr, mc):
+    # Eq. (7)-(8) by counting: ids 0, 1, 2, ... over the rows of the job matrix
+    ys, xs = [], []
+    for y in range(mr):
+        for x in range(mc):
+            ys.append(y)
+            xs.append(x)
+    return np.array(ys), np.array(xs)
+
+
+@pytest.mark.parametrize("mr,mc", [(1, 1), (1, 7), (7, 1), (5, 9), (33, 17), (128, 128), (3, 200)])
+@pytest.mark.parametrize("order,band", [(0, 1), (1, 1), (1, 2), (1, 4), (1, 8), (1, 16)])
+def test_rect_order(mr, mc, order, band):
+    import paper_1605_01584_amd as pcc
+    cfg = pcc.TileCfg(128, order, band, 0)
+    yt, xt = pcc.rect_tile_order_host(mr, mc, cfg, 0, mr * mc)
+    assert yt.min() >= 0 and yt.max() < mr and xt.min() >= 0 and xt.max() < mc
+    ids = yt * mc + xt
+    np.testing.assert_array_equal(np.sort(ids), np.arange(mr * mc))   # a bijection
+    if order == 0 or band == 1:
+        ry, rx = _rect_row_major(mr, mc)
+        np.testing.assert_array_equal(yt, ry)
+        np.testing.assert_array_equal(xt, rx)
+    else:
+        # bands of `band` tile rows, each walked column by column, top to bottom
+        b = yt // band
+        assert np.all(np.diff(b) >= 0)
+        for bb in np.unique(b):
+            sel = b == bb
+            key = xt[sel] * band + (yt[sel] - bb * band)
+            assert np.all(np.diff(key) > 0)
+    # any window gives the same cells as the whole range
+    if mr * mc > 3:
+        y2, x2 = pcc.rect_tile_order_host(mr, mc, cfg, 2, mr * mc - 3)
+        np.testing.assert_array_equal(y2, yt[2:mr * mc - 1])
+        np.testing.assert_array_equal(x2, xt[2:mr * mc - 1])

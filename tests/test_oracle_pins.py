@@ -229,3 +229,46 @@ def test_planted_pairs_follow_model(oracle_mod):
     # sampling error of r around rho is about (1 - rho^2)/sqrt(l)
     assert np.all(np.abs(r - rho) <= 6 * (1 - rho ** 2) / np.sqrt(256) + 1e-3)
     assert len(set(pl.u.tolist()) | set(pl.v.tolist())) == 40
+
+
+@pytest.mark.parametrize("nx,ny,l", [(1, 1, 2), (3, 7, 5), (17, 9, 33), (40, 64, 256)])
+def test_xy_vs_numpy_corrcoef(oracle_mod, nx, ny, l):
+    # non-symmetric job matrix (two variable sets): the cross block of
+    # numpy's correlation matrix of the stacked rows, in (X row, Y row) order
+    rng = np.random.default_rng(300 + nx + 5 * ny + l)
+    X = rng.standard_normal((nx, l)) * rng.uniform(0.1, 10, (nx, 1))
+    Y = rng.standard_normal((ny, l)) + rng.uniform(-5, 5, (ny, 1))
+    r = oracle_mod.pearson_xy(X, Y)
+    C = np.corrcoef(np.vstack([X, Y]))
+    assert r.shape == (nx, ny)
+    np.testing.assert_allclose(r, C[:nx, nx:], rtol=0, atol=1e-12)
+
+
+def test_xy_closed_form_and_orientation(oracle_mod):
+    # Y_j = a_j u + c_j w with u, w centred and orthogonal of equal norm:
+    # r(u, Y_j) = a_j / sqrt(a_j^2 + c_j^2) exactly; row 1 of X is -u.
+    l = 64
+    k = np.arange(l)
+    u = np.cos(2 * np.pi * 3 * k / l)
+    w = np.sin(2 * np.pi * 5 * k / l)
+    a = np.array([1.0, -2.0, 0.5, 3.0])
+    c = np.array([1.0, 1.0, 2.0, 0.0])
+    Y = a[:, None] * u + c[:, None] * w
+    r = oracle_mod.pearson_xy(np.stack([u, -u]), Y)
+    ref = a / np.sqrt(a * a + c * c)
+    np.testing.assert_allclose(r[0], ref, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(r[1], -ref, rtol=0, atol=1e-14)
+
+
+def test_xy_with_itself_is_the_symmetric_matrix(oracle_mod):
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((23, 41))
+    X[5] = 2.0                                   # constant row: NaN everywhere
+    r = oracle_mod.pearson_xy(X, X)
+    packed = oracle_mod.pearson_packed(X)
+    iu = np.triu_indices(23, 1)
+    np.testing.assert_array_equal(r[iu], packed)          # same arithmetic, bit for bit
+    np.testing.assert_array_equal(r.T[iu], packed)        # Eq. (1) is symmetric
+    d = np.diag(r).copy()
+    assert np.isnan(d[5]) and np.all(np.isnan(r[5])) and np.all(np.isnan(r[:, 5]))
+    np.testing.assert_allclose(np.delete(d, 5), 1.0, rtol=0, atol=1e-15)
