@@ -13,7 +13,7 @@
  *     in the denominator (as the variable-transformation algorithm computes
  *     it): mean, sum of squared deviations, reciprocal square root, scaled
  *     deviations;
- *   - non-symmetric all-pairs (two variable sets, Sec. III-A) is Eq. (1)
+ *   - non-symmetric all-pairs (two variable sets, Sec. III-B) is Eq. (1)
  *     for every cell of the nx x ny job matrix, row by row;
  *   - job numbering follows the symmetric all-pairs framework (Sec. III-B):
  *     upper-triangle cells numbered left to right, top to bottom, by
@@ -102,7 +102,7 @@ int oracle_pearson_packed(const double *X, int64_t n, int64_t l, int64_t ld,
   return 0;
 }
 
-/* Non-symmetric all-pairs (Sec. III-A): r of row i of X (nx rows, pitch
+/* Non-symmetric all-pairs (Sec. III-B): r of row i of X (nx rows, pitch
  * ldx) and row j of Y (ny rows, pitch ldy), both of l samples, written to
  * out[i * ny + j] for every i and j (the whole job matrix, row by row). */
 int oracle_pearson_xy(const double *X, int64_t nx, int64_t ldx, const double *Y, int64_t ny,
