@@ -327,6 +327,32 @@ def main():
                         "mfma_frac": 2.0 * MFMA_PER_MAC[mode] * ps_xy / (txy * 1e-3) / PEAK[dt]}
         del zx, zy, rxy
         torch.cuda.empty_cache()
+        # multi-pass all pairs into pinned host memory (8 tile rows per pass)
+        log("[bench] multi-pass to host")
+        host = torch.empty(npairs, dtype=torch.float32, pin_memory=True)
+        rpp = cfg.band if cfg.order == 1 else 8
+        dev_buf = torch.empty(pcc.stream_buffer_bytes(zd, cfg, rpp), dtype=torch.uint8, device=dev)
+        copy_stream = torch.cuda.Stream(device=dev)
+        pcc.allpairs_to_host(z, zd, rpp, cfg, out=host, dev_buf=dev_buf, copy_stream=copy_stream)
+        t0 = time.perf_counter()
+        pcc.allpairs_to_host(z, zd, rpp, cfg, out=host, dev_buf=dev_buf, copy_stream=copy_stream)
+        t_stream = (time.perf_counter() - t0) * 1e3
+        # the PCIe side alone: one device-to-host copy of the same bytes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host.copy_(r, non_blocking=True)
+        torch.cuda.synchronize()
+        t_d2h = (time.perf_counter() - t0) * 1e3
+        m_tiles = (n + cfg.tile - 1) // cfg.tile
+        extras["to_host"] = {
+            "workload": f"n={n} l={l} {mode}, {rpp} tile rows per pass, "
+                        f"{(m_tiles + rpp - 1) // rpp} passes, pinned host triangle",
+            "ms": t_stream, "pair_samples_per_s": pair_samples / (t_stream * 1e-3),
+            "host_GB_per_s": npairs * 4 / (t_stream * 1e-3) / 1e9,
+            "plain_d2h_copy_ms": t_d2h, "plain_d2h_GB_per_s": npairs * 4 / (t_d2h * 1e-3) / 1e9,
+            "compute_only_ms": tile_avg}
+        del host, dev_buf
+        torch.cuda.empty_cache()
         log("[bench] calibration: MFMA loop, device copy, hipBLASLt GEMM")
         extras["calibration"] = calibration(dev, stream)
 

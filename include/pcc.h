@@ -115,6 +115,12 @@ const char *pcc_status_string(pcc_status s);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t pcc_version(void);
 
+/* The hipError_t of the last HIP call that failed inside a pcc_* call on
+ * the calling thread (0 if none has), and its name (static string).  It is
+ * what a PCC_E_HIP result stands for; it is not reset by later successes. */
+int32_t pcc_last_hip_error(void);
+const char *pcc_last_hip_error_string(void);
+
 /* Fill *out with the Z layout for n profiles of l samples in `mode`.
  * Host only, pure.  Requires 1 <= n <= 2^31-1 and 2 <= l <= 2^21 (a
  * 256-row panel of Z stays within 2 GiB, so tile loads use 32-bit offsets).
@@ -158,6 +164,40 @@ pcc_status pcc_allpairs(const pcc_zdesc *zd, const void *z, float *r,
  * precision).  r: device, n(n-1)/2 doubles. */
 pcc_status pcc_allpairs_f64(const pcc_zdesc *zd, const void *z, double *r,
                             const pcc_tile_cfg *cfg, void *workspace, void *stream);
+
+/* ---- Multi-pass all pairs into host memory ------------------------------
+ * For triangles larger than device memory, or results wanted on the host:
+ * the multi-pass execution of Sec. III-C with the double buffering of the
+ * asynchronous execution algorithm.  The tile-id range [0, m(m+1)/2) is cut
+ * into passes of `rows_per_pass` whole tile rows (a multiple of cfg->band in
+ * the banded order), so a pass covers the contiguous id range
+ * [F_m(y_a), F_m(y_b)) (Eq. (17)) and its pairs are one contiguous slice of
+ * the packed triangle.  Pass p is computed into device buffer p % 2 on
+ * compute_stream, then copied by one asynchronous device-to-host copy on
+ * copy_stream straight to its final place in r_host, while pass p + 1
+ * computes into the other buffer.  After pass p's copy has landed,
+ * on_pass(first, count, user) (nullable) is called on the calling thread
+ * with the slice [first, first + count) of the packed triangle; meanwhile
+ * the next pass computes (the host-side processing of the paper's loop).
+ *
+ *   r_host   host, n(n-1)/2 floats, the packed triangle as pcc_allpairs
+ *            writes it.  Should be pinned (hipHostMalloc) for asynchronous
+ *            copies.
+ *   dev_buf  device, at least pcc_stream_buffer_bytes(zd, cfg,
+ *            rows_per_pass) bytes (two pass buffers).
+ * Blocking: returns after every pass has landed in r_host.  compute_stream
+ * and copy_stream may be equal (no overlap then).  Creates and destroys
+ * four HIP events per call; allocates no memory. */
+typedef void (*pcc_pass_fn)(int64_t first, int64_t count, void *user);
+
+size_t pcc_stream_buffer_bytes(const pcc_zdesc *zd, const pcc_tile_cfg *cfg,
+                               int64_t rows_per_pass);
+
+pcc_status pcc_allpairs_to_host(const pcc_zdesc *zd, const void *z, float *r_host,
+                                int64_t rows_per_pass, void *dev_buf,
+                                size_t dev_buf_bytes, const pcc_tile_cfg *cfg,
+                                pcc_pass_fn on_pass, void *user,
+                                void *compute_stream, void *copy_stream);
 
 /* Thresholded edge list (a4 (ii)): every pair y < x with |r| >= thr (r
  * clamped as above; NaN never qualifies) is appended as ij[2s] = y,

@@ -6,7 +6,7 @@ used for device memory and streams.  Importing this package fails loudly if
 the library has not been built (``python -m paper_1605_01584_amd.build``).
 
 Names follow the C ABI: ``z_layout``, ``normalize``, ``allpairs``,
-``allpairs_f64``, ``threshold_edges``, ``allpairs_xy``,
+``allpairs_f64``, ``allpairs_to_host``, ``threshold_edges``, ``allpairs_xy``,
 ``threshold_edges_xy``, ``permtest``, ``BatchPlan``, the job maps and
 ``autotune``.
 """
@@ -25,6 +25,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first "
         "(python -m paper_1605_01584_amd.build). There is no CPU fallback.")
+
+# One HIP runtime per process: torch's HIP libraries load the runtime bundled
+# with torch under the name "libamdhip64.so" (through their own RPATH), while
+# libpcc.so asks for "libamdhip64.so.7".  With torch loaded first, the
+# request of libpcc.so matches the SONAME already in the process and both
+# share torch's runtime; the other order would load a second runtime, which
+# then sees no device.  So torch is imported before libpcc.so is opened.
+import torch as _torch_for_hip_runtime  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -78,6 +86,8 @@ def _sig(name, res, *args):
 
 _sig("pcc_status_string", ctypes.c_char_p, _i32)
 _sig("pcc_version", _i32)
+_sig("pcc_last_hip_error", _i32)
+_sig("pcc_last_hip_error_string", ctypes.c_char_p)
 _sig("pcc_z_layout", _i32, _i64, _i64, _i32, _zdp)
 _sig("pcc_default_cfg", _i32, _zdp, _cfgp)
 _sig("pcc_normalize", _i32, _vp, _i32, _i64, _zdp, _vp, _vp, _vp, _vp)
@@ -85,6 +95,10 @@ _sig("pcc_workspace_size", ctypes.c_size_t, _zdp, _i32)
 _sig("pcc_allpairs", _i32, _zdp, _vp, _vp, _cfgp, _vp, _vp)
 _sig("pcc_allpairs_f64", _i32, _zdp, _vp, _vp, _cfgp, _vp, _vp)
 _sig("pcc_threshold_edges", _i32, _zdp, _vp, _f32, _vp, _vp, _i64, _vp, _cfgp, _vp, _vp)
+PASS_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p)
+_sig("pcc_stream_buffer_bytes", ctypes.c_size_t, _zdp, _cfgp, _i64)
+_sig("pcc_allpairs_to_host", _i32, _zdp, _vp, _vp, _i64, _vp, ctypes.c_size_t, _cfgp, PASS_FN,
+     _vp, _vp, _vp)
 _sig("pcc_allpairs_xy", _i32, _zdp, _vp, _zdp, _vp, _vp, _i64, _cfgp, _vp, _vp)
 _sig("pcc_threshold_edges_xy", _i32, _zdp, _vp, _zdp, _vp, _f32, _vp, _vp, _i64, _vp, _cfgp, _vp,
      _vp)
@@ -109,9 +123,11 @@ _sig("pcc_autotune", _i32, _zdp, _vp, _vp, _cfgp, _i32, _i32, _cfgp, _vp, _vp)
 _sig("pcc_device_cus", _i32)
 
 EXPORTED = [
-    "pcc_status_string", "pcc_version", "pcc_z_layout", "pcc_default_cfg", "pcc_normalize",
+    "pcc_status_string", "pcc_version", "pcc_last_hip_error", "pcc_last_hip_error_string",
+    "pcc_z_layout", "pcc_default_cfg", "pcc_normalize",
     "pcc_workspace_size", "pcc_allpairs", "pcc_allpairs_f64", "pcc_threshold_edges",
     "pcc_edges_status", "pcc_allpairs_xy", "pcc_threshold_edges_xy", "pcc_rect_tile_order_host",
+    "pcc_stream_buffer_bytes", "pcc_allpairs_to_host",
     "pcc_permtest", "pcc_permtest_max_l", "pcc_batch_workspace_size", "pcc_batch_plan_create",
     "pcc_batch_plan_launch", "pcc_batch_plan_jobs", "pcc_batch_plan_destroy", "pcc_job_of_cell",
     "pcc_cell_of_job", "pcc_packed_index", "pcc_packed_cell", "pcc_cells_host",
@@ -122,7 +138,11 @@ EXPORTED = [
 class PccError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__(f"{where}: {status_string(status)}")
+        msg = f"{where}: {status_string(status)}"
+        if status == PCC_E_HIP:
+            self.hip_error = _lib.pcc_last_hip_error()
+            msg += f" ({_lib.pcc_last_hip_error_string().decode()} = {self.hip_error})"
+        super().__init__(msg)
 
 
 def status_string(s: int) -> str:
@@ -297,6 +317,43 @@ def allpairs_f64(z, zd: ZDesc, cfg: Optional[TileCfg] = None, out=None, stream=N
     _check(_lib.pcc_allpairs_f64(ctypes.byref(zd), _dev_ptr(z, "z"), _dev_ptr(out, "r"),
                                  ctypes.byref(cfg) if cfg is not None else None, None,
                                  _stream(torch, stream)), "pcc_allpairs_f64")
+    return out
+
+
+def stream_buffer_bytes(zd: ZDesc, cfg: Optional[TileCfg], rows_per_pass: int) -> int:
+    return _lib.pcc_stream_buffer_bytes(ctypes.byref(zd),
+                                        ctypes.byref(cfg) if cfg is not None else None,
+                                        rows_per_pass)
+
+
+def allpairs_to_host(z, zd: ZDesc, rows_per_pass: int, cfg: Optional[TileCfg] = None, out=None,
+                     on_pass=None, dev_buf=None, stream=None, copy_stream=None):
+    """Multi-pass all pairs into host memory: passes of rows_per_pass tile rows,
+    double-buffered on the device, each copied to its place in `out` (pinned
+    host float32, n(n-1)/2) while the next pass computes.  on_pass(first, count)
+    is called after each slice has landed.  Blocking."""
+    torch = _torch()
+    if cfg is None:
+        cfg = default_cfg(zd)
+    need = stream_buffer_bytes(zd, cfg, rows_per_pass)
+    if need == 0:
+        raise ValueError("invalid layout, schedule or rows_per_pass")
+    npairs = zd.n * (zd.n - 1) // 2
+    if out is None:
+        out = torch.empty(npairs, dtype=torch.float32, pin_memory=True)
+    if out.is_cuda or out.dtype != torch.float32 or out.numel() < npairs or not out.is_contiguous():
+        raise ValueError("out must be a contiguous host float32 tensor of n(n-1)/2")
+    if dev_buf is None:
+        dev_buf = torch.empty(need, dtype=torch.uint8, device=z.device)
+    cs = stream if stream is not None else torch.cuda.current_stream()
+    xs = copy_stream if copy_stream is not None else torch.cuda.Stream(device=z.device)
+    cb = PASS_FN(lambda f, c, u: on_pass(f, c)) if on_pass is not None else PASS_FN()
+    _check(_lib.pcc_allpairs_to_host(ctypes.byref(zd), _dev_ptr(z, "z"),
+                                     ctypes.c_void_p(out.data_ptr()), rows_per_pass,
+                                     _dev_ptr(dev_buf, "dev_buf"),
+                                     dev_buf.numel() * dev_buf.element_size(), ctypes.byref(cfg),
+                                     cb, None, ctypes.c_void_p(cs.cuda_stream),
+                                     ctypes.c_void_p(xs.cuda_stream)), "pcc_allpairs_to_host")
     return out
 
 

@@ -16,6 +16,9 @@ hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const p
                            int grid, hipStream_t st);
 hipError_t launch_allpairs_f64(const pcc_zdesc &zd, const void *z, double *r,
                                const pcc_tile_cfg &cfg, int grid, hipStream_t st);
+hipError_t launch_allpairs_range(const pcc_zdesc &zd, const void *z, float *r, int64_t roff,
+                                 const pcc_tile_cfg &cfg, int64_t j0, int64_t j1, int grid,
+                                 hipStream_t st);
 hipError_t launch_edges(const pcc_zdesc &zd, const void *z, float thr, int32_t *ij, float *rv,
                         int64_t cap, int64_t *count, const pcc_tile_cfg &cfg, int grid,
                         hipStream_t st);
@@ -94,9 +97,17 @@ int grid_for(const pcc_zdesc &zd, const pcc_tile_cfg &cfg, int epi, int64_t ny =
   return (int)g;
 }
 
-pcc_status hip_status(hipError_t e) { return e == hipSuccess ? PCC_OK : PCC_E_HIP; }
+pcc_status hip_status(hipError_t e) { return note_hip(e) == hipSuccess ? PCC_OK : PCC_E_HIP; }
+
+thread_local hipError_t g_last_hip = hipSuccess;
 
 }  // namespace
+
+hipError_t note_hip(hipError_t e) {
+  if (e != hipSuccess) g_last_hip = e;
+  return e;
+}
+
 }  // namespace pcc
 
 using namespace pcc;
@@ -118,6 +129,10 @@ const char *pcc_status_string(pcc_status s) {
 }
 
 int32_t pcc_version(void) { return 10000; }
+
+int32_t pcc_last_hip_error(void) { return (int32_t)g_last_hip; }
+
+const char *pcc_last_hip_error_string(void) { return hipGetErrorName(g_last_hip); }
 
 pcc_status pcc_z_layout(int64_t n, int64_t l, pcc_mode_t mode, pcc_zdesc *out) {
   if (!out) return PCC_E_ARG;
@@ -208,6 +223,100 @@ pcc_status pcc_allpairs_f64(const pcc_zdesc *zd, const void *z, double *r,
   if (s != PCC_OK) return s;
   return hip_status(launch_allpairs_f64(*zd, z, r, c, grid_for(*zd, c, kEpiPackedF64),
                                         (hipStream_t)stream));
+}
+
+// Packed-triangle slice of the tile rows [ya, yb) (clamped to the rows
+// that hold pairs): [tri_F(n-1, ya T), tri_F(n-1, yb T)).
+static void pass_slice(int64_t n, int64_t T, int64_t ya, int64_t yb, int64_t *first,
+                       int64_t *count) {
+  const int64_t a = std::min(n - 1, ya * T), b = std::min(n - 1, yb * T);
+  *first = tri_F(n - 1, a);
+  *count = tri_F(n - 1, b) - *first;
+}
+
+size_t pcc_stream_buffer_bytes(const pcc_zdesc *zd, const pcc_tile_cfg *cfg,
+                               int64_t rows_per_pass) {
+  pcc_tile_cfg c;
+  if (check_zdesc(zd) != PCC_OK || zd->n < 2 || rows_per_pass < 1 ||
+      check_cfg(*zd, cfg, c) != PCC_OK)
+    return 0;
+  // the first pass is the largest (the rows nearest the top are the longest)
+  int64_t first = 0, count = 0;
+  pass_slice(zd->n, c.tile, 0, rows_per_pass, &first, &count);
+  return 2 * (size_t)count * sizeof(float);
+}
+
+pcc_status pcc_allpairs_to_host(const pcc_zdesc *zd, const void *z, float *r_host,
+                                int64_t rows_per_pass, void *dev_buf, size_t dev_buf_bytes,
+                                const pcc_tile_cfg *cfg, pcc_pass_fn on_pass, void *user,
+                                void *compute_stream, void *copy_stream) {
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (zd->n < 2) return PCC_E_SHAPE;
+  if (!z || !r_host || rows_per_pass < 1) return PCC_E_ARG;
+  pcc_tile_cfg c;
+  s = check_cfg(*zd, cfg, c);
+  if (s != PCC_OK) return s;
+  // a pass must be a whole number of bands to be a contiguous id range
+  if (c.order == 1 && c.band > 1 && rows_per_pass % c.band != 0) return PCC_E_ARG;
+  const size_t need = pcc_stream_buffer_bytes(zd, &c, rows_per_pass);
+  if (!dev_buf || dev_buf_bytes < need) return PCC_E_WORKSPACE;
+  const int64_t n = zd->n, T = c.tile, m = (n + T - 1) / T;
+  float *buf[2] = {(float *)dev_buf, (float *)dev_buf + need / 2 / sizeof(float)};
+  hipStream_t cs = (hipStream_t)compute_stream, xs = (hipStream_t)copy_stream;
+  const int grid = grid_for(*zd, c, kEpiPacked);
+
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // K0 K1 C0 C1
+  for (int k = 0; k < 4; ++k)
+    if (note_hip(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming)) != hipSuccess) {
+      for (int q = 0; q < k; ++q) hipEventDestroy(ev[q]);
+      return PCC_E_HIP;
+    }
+  hipEvent_t *K = ev, *C = ev + 2;
+  pcc_status rs = PCC_OK;
+  int64_t prev_first = 0, prev_count = 0;
+  bool have_prev = false;
+  for (int64_t ya = 0, p = 0; ya < m && rs == PCC_OK; ya += rows_per_pass, ++p) {
+    const int64_t yb = std::min(m, ya + rows_per_pass);
+    const int b = (int)(p & 1);
+    int64_t first = 0, count = 0;
+    pass_slice(n, T, ya, yb, &first, &count);
+    // buffer b is free once the copy of pass p - 2 has landed
+    if (p >= 2 && note_hip(hipStreamWaitEvent(cs, C[b], 0)) != hipSuccess) rs = PCC_E_HIP;
+    if (rs == PCC_OK &&
+        (note_hip(launch_allpairs_range(*zd, z, buf[b], first, c, tri_F(m, ya), tri_F(m, yb), grid,
+                                        cs)) != hipSuccess ||
+         note_hip(hipEventRecord(K[b], cs)) != hipSuccess ||
+         note_hip(hipStreamWaitEvent(xs, K[b], 0)) != hipSuccess ||
+         (count > 0 && note_hip(hipMemcpyAsync(r_host + first, buf[b], (size_t)count * sizeof(float),
+                                               hipMemcpyDeviceToHost, xs)) != hipSuccess) ||
+         note_hip(hipEventRecord(C[b], xs)) != hipSuccess))
+      rs = PCC_E_HIP;
+    // host side of the previous pass, overlapped with this pass's kernel
+    if (rs == PCC_OK && have_prev) {
+      if (note_hip(hipEventSynchronize(C[1 - b])) != hipSuccess)
+        rs = PCC_E_HIP;
+      else if (on_pass && prev_count > 0)
+        on_pass(prev_first, prev_count, user);
+    }
+    prev_first = first;
+    prev_count = count;
+    have_prev = true;
+  }
+  if (have_prev) {
+    // the last pass (its buffer is the one recorded last)
+    const int64_t passes = (m + rows_per_pass - 1) / rows_per_pass;
+    const int b = (int)((passes - 1) & 1);
+    if (note_hip(hipEventSynchronize(C[b])) != hipSuccess) {
+      rs = PCC_E_HIP;
+    } else if (rs == PCC_OK && on_pass && prev_count > 0) {
+      on_pass(prev_first, prev_count, user);
+    }
+  }
+  hipStreamSynchronize(xs);
+  hipStreamSynchronize(cs);
+  for (int k = 0; k < 4; ++k) hipEventDestroy(ev[k]);
+  return rs;
 }
 
 pcc_status pcc_threshold_edges(const pcc_zdesc *zd, const void *z, float thr, int32_t *ij,
@@ -380,8 +489,8 @@ pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_
   }
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return PCC_E_HIP;
-  if (hipEventCreate(&e1) != hipSuccess) {
+  if (note_hip(hipEventCreate(&e0)) != hipSuccess) return PCC_E_HIP;
+  if (note_hip(hipEventCreate(&e1)) != hipSuccess) {
     hipEventDestroy(e0);
     return PCC_E_HIP;
   }
@@ -397,8 +506,10 @@ pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_
     const int grid = grid_for(*zd, c, kEpiPacked);
     std::vector<float> ts;
     for (int rep = 0; rep <= reps && rs == PCC_OK; ++rep) {  // rep 0 warms up
-      if (hipEventRecord(e0, st) != hipSuccess || launch_allpairs(*zd, z, r, c, grid, st) != hipSuccess ||
-          hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      if (note_hip(hipEventRecord(e0, st)) != hipSuccess ||
+          note_hip(launch_allpairs(*zd, z, r, c, grid, st)) != hipSuccess ||
+          note_hip(hipEventRecord(e1, st)) != hipSuccess ||
+          note_hip(hipEventSynchronize(e1)) != hipSuccess) {
         rs = PCC_E_HIP;
         break;
       }

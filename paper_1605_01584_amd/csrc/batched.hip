@@ -205,14 +205,14 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
   hipStream_t st = (hipStream_t)stream;
   unsigned char *ws = (unsigned char *)workspace;
   BatchDesc *ddesc = (BatchDesc *)(ws + kCounterBytes);
-  if (hipMemcpyAsync(ddesc, ds.data(), ds.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
+  if (note_hip(hipMemcpyAsync(ddesc, ds.data(), ds.size() * sizeof(BatchDesc),
+                              hipMemcpyHostToDevice, st)) != hipSuccess ||
+      note_hip(hipStreamSynchronize(st)) != hipSuccess)
     return PCC_E_HIP;
 
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+  if (note_hip(hipGetDevice(&dev)) != hipSuccess ||
+      note_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return PCC_E_HIP;
 
   pcc_batch_plan *p = (pcc_batch_plan *)calloc(1, sizeof(pcc_batch_plan));
@@ -222,12 +222,12 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
   p->jobs = jobs;
   p->rows = rows;
   hipStream_t cs = nullptr;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+  if (note_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
     free(p);
     return PCC_E_HIP;
   }
   pcc_status rs = PCC_OK;
-  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+  if (note_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess) {
     rs = PCC_E_HIP;
   } else {
     unsigned long long *counter = (unsigned long long *)ws;
@@ -241,13 +241,14 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
       case PCC_FP16: e = launch_batch<PCC_FP16>(ddesc, D, rows, jobs, counter, cus, cs); break;
     }
     hipGraph_t g = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    note_hip(e);
+    const hipError_t e2 = note_hip(hipStreamEndCapture(cs, &g));
     if (e != hipSuccess || e2 != hipSuccess || !g) {
       rs = PCC_E_HIP;
       if (g) hipGraphDestroy(g);
     } else {
       p->graph = g;
-      if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      if (note_hip(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
         hipGraphDestroy(g);
         p->graph = nullptr;
         rs = PCC_E_HIP;
@@ -265,7 +266,7 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
 
 pcc_status pcc_batch_plan_launch(pcc_batch_plan *plan, void *stream) {
   if (!plan || !plan->exec) return PCC_E_ARG;
-  return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? PCC_OK : PCC_E_HIP;
+  return note_hip(hipGraphLaunch(plan->exec, (hipStream_t)stream)) == hipSuccess ? PCC_OK : PCC_E_HIP;
 }
 
 int64_t pcc_batch_plan_jobs(const pcc_batch_plan *plan) { return plan ? plan->jobs : -1; }
@@ -273,8 +274,8 @@ int64_t pcc_batch_plan_jobs(const pcc_batch_plan *plan) { return plan ? plan->jo
 pcc_status pcc_batch_plan_destroy(pcc_batch_plan *plan) {
   if (!plan) return PCC_E_ARG;
   pcc_status s = PCC_OK;
-  if (plan->exec && hipGraphExecDestroy(plan->exec) != hipSuccess) s = PCC_E_HIP;
-  if (plan->graph && hipGraphDestroy(plan->graph) != hipSuccess) s = PCC_E_HIP;
+  if (plan->exec && note_hip(hipGraphExecDestroy(plan->exec)) != hipSuccess) s = PCC_E_HIP;
+  if (plan->graph && note_hip(hipGraphDestroy(plan->graph)) != hipSuccess) s = PCC_E_HIP;
   free(plan);
   return s;
 }

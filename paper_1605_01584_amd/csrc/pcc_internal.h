@@ -108,6 +108,10 @@ PCC_HD float bf16_bits_to_f32(uint16_t h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
+// The last HIP error a library call met on this thread (for
+// pcc_last_hip_error); returns e so call sites can wrap a HIP call.
+hipError_t note_hip(hipError_t e);
+
 // Layout constants.
 constexpr int kChunkBytes = 128;
 constexpr int kRowPadMultiple = 256;

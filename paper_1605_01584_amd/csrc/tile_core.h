@@ -83,6 +83,7 @@ struct ZView {
 struct EpiArgs {
   float *r;                 // packed triangle, or nx x ldr rectangle
   double *r64;              // packed triangle in FP64
+  int64_t roff;             // packed: index of r[0] in the whole triangle (a slice)
   int64_t ldr;              // rectangle row pitch
   float thr;                // edges: |r| >= thr
   int32_t *ij;
@@ -120,7 +121,7 @@ template <int EPI> struct Epi {
     if constexpr (kRect)
       return y * ea.ldr;
     else
-      return tri_F(zv.n - 1, y) - 1 - y;
+      return tri_F(zv.n - 1, y) - 1 - y - ea.roff;
   }
   static __device__ __forceinline__ bool keep(const ZView &zv, int64_t y, int64_t x) {
     if constexpr (kRect)

@@ -21,7 +21,8 @@ struct UniformArgs {
   EpiArgs ea;
   int64_t mr;     // tile rows
   int64_t mc;     // tile columns (non-symmetric)
-  int64_t njobs;  // mr(mr+1)/2 or mr mc
+  int64_t j0;     // first tile id of this launch
+  int64_t njobs;  // one past the last tile id: mr(mr+1)/2 or mr mc for a whole run
   int32_t order;
   int32_t band;
 };
@@ -32,7 +33,7 @@ template <int MODE, int TILE, int EPI>
 __global__ __launch_bounds__(kTileThreads, 1) void tile_kernel(UniformArgs a) {
   __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
   const int64_t G = gridDim.x;
-  for (int64_t J = xcd_slot(blockIdx.x, G); J < a.njobs; J += G) {
+  for (int64_t J = a.j0 + xcd_slot(blockIdx.x, G); J < a.njobs; J += G) {
     Cell tc;
     if constexpr (is_rect<EPI>())
       tc = rect_cell(a.mr, a.mc, a.order, a.band, J);
@@ -118,7 +119,8 @@ hipError_t launch(int mode, UniformArgs a, int tile, int epi, int grid, hipStrea
   const void *k = kernel_for(mode, tile, epi);
   if (!k) return hipErrorInvalidValue;
   if (grid < 1) grid = 1;
-  if (a.njobs < grid) grid = (int)a.njobs;
+  if (a.njobs - a.j0 < grid) grid = (int)(a.njobs - a.j0);
+  if (grid < 1) return hipSuccess;  // empty range
   void *args[] = {(void *)&a};
   return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, st);
 }
@@ -149,6 +151,20 @@ hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const p
                            int grid, hipStream_t st) {
   UniformArgs a = make_args(zd, z, cfg);
   a.ea.r = r;
+  return launch(zd.mode, a, cfg.tile, EPI_PACKED, grid, st);
+}
+
+// Tile ids [j0, j1) of the symmetric schedule, r holding the packed
+// triangle from index roff on (a contiguous slice when [j0, j1) is a whole
+// number of tile rows, or of bands in the banded order).
+hipError_t launch_allpairs_range(const pcc_zdesc &zd, const void *z, float *r, int64_t roff,
+                                 const pcc_tile_cfg &cfg, int64_t j0, int64_t j1, int grid,
+                                 hipStream_t st) {
+  UniformArgs a = make_args(zd, z, cfg);
+  a.ea.r = r;
+  a.ea.roff = roff;
+  a.j0 = j0;
+  a.njobs = j1;
   return launch(zd.mode, a, cfg.tile, EPI_PACKED, grid, st);
 }
 

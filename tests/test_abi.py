@@ -203,3 +203,44 @@ def test_fp64_and_xy_argument_errors():
     cfg = pcc.TileCfg(128, 1, 4, 0)
     assert lib.pcc_rect_tile_order_host(3, 4, ctypes.byref(cfg), 10, 5, fake, fake) == pcc.PCC_E_SHAPE
     assert lib.pcc_rect_tile_order_host(0, 4, ctypes.byref(cfg), 0, 1, fake, fake) == pcc.PCC_E_ARG
+
+
+def test_stream_to_host_argument_errors():
+    import paper_1605_01584_amd as pcc
+    lib = pcc._lib
+    fake = ctypes.c_void_p(0x1000)
+    zd = pcc.z_layout(3000, 100, "split")
+    cfg = pcc.TileCfg(128, 1, 4, 0)
+    need = pcc.stream_buffer_bytes(zd, cfg, 8)
+    # the first pass is the largest: rows 0 .. 8*128-1 of the triangle, two buffers
+    first_rows = 8 * 128
+    assert need == 2 * 4 * sum(3000 - 1 - y for y in range(first_rows))
+    assert pcc.stream_buffer_bytes(zd, cfg, 0) == 0
+    nofn = pcc.PASS_FN()
+    call = lib.pcc_allpairs_to_host
+    # a pass must be a whole number of bands
+    assert call(ctypes.byref(zd), fake, fake, 6, fake, need, ctypes.byref(cfg), nofn, None, None,
+                None) == pcc.PCC_E_ARG
+    # too small a device buffer, missing buffer
+    assert call(ctypes.byref(zd), fake, fake, 8, fake, need - 1, ctypes.byref(cfg), nofn, None,
+                None, None) == pcc.PCC_E_WORKSPACE
+    assert call(ctypes.byref(zd), fake, fake, 8, None, need, ctypes.byref(cfg), nofn, None, None,
+                None) == pcc.PCC_E_WORKSPACE
+    assert call(ctypes.byref(zd), fake, None, 8, fake, need, ctypes.byref(cfg), nofn, None, None,
+                None) == pcc.PCC_E_ARG
+    one = pcc.z_layout(1, 100, "split")
+    assert call(ctypes.byref(one), fake, fake, 8, fake, need, ctypes.byref(cfg), nofn, None, None,
+                None) == pcc.PCC_E_SHAPE
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    # importing the package before torch must not load a second HIP runtime
+    import subprocess
+    import sys
+    code = ("import paper_1605_01584_amd, torch\n"
+            "m = open('/proc/self/maps').read()\n"
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
