@@ -333,16 +333,21 @@ def main():
         rpp = cfg.band if cfg.order == 1 else 8
         dev_buf = torch.empty(pcc.stream_buffer_bytes(zd, cfg, rpp), dtype=torch.uint8, device=dev)
         copy_stream = torch.cuda.Stream(device=dev)
+        def wall_best(fn, reps=3):   # blocking calls: host clock, best of reps
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return min(ts)
         pcc.allpairs_to_host(z, zd, rpp, cfg, out=host, dev_buf=dev_buf, copy_stream=copy_stream)
-        t0 = time.perf_counter()
-        pcc.allpairs_to_host(z, zd, rpp, cfg, out=host, dev_buf=dev_buf, copy_stream=copy_stream)
-        t_stream = (time.perf_counter() - t0) * 1e3
+        t_stream = wall_best(lambda: pcc.allpairs_to_host(z, zd, rpp, cfg, out=host,
+                                                          dev_buf=dev_buf,
+                                                          copy_stream=copy_stream))
         # the PCIe side alone: one device-to-host copy of the same bytes
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        host.copy_(r, non_blocking=True)
-        torch.cuda.synchronize()
-        t_d2h = (time.perf_counter() - t0) * 1e3
+        t_d2h = wall_best(lambda: host.copy_(r, non_blocking=True))
         m_tiles = (n + cfg.tile - 1) // cfg.tile
         extras["to_host"] = {
             "workload": f"n={n} l={l} {mode}, {rpp} tile rows per pass, "
