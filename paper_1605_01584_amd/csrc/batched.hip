@@ -100,12 +100,16 @@ __global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const Batch
     ZView zv{d.z, d.row_bytes, d.n, d.nchunks, d.scale, d.z, d.n};
     EpiArgs ea{};
     ea.r = d.r;
+    // Consecutive jobs may use different tile sizes, whose stage copies give
+    // a wave different LDS units: the previous job's last copies (possibly
+    // still in flight) must land before any wave starts the next job's.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     if (d.tile == 128)
       do_tile<MODE, 128, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
     else
       do_tile<MODE, 256, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
-    // do_tile ends with a barrier after its last LDS read, and every thread
-    // has read jslot before it, so thread 0 may overwrite jslot now.
+    // do_tile begins with a barrier, which every thread reaches after it has
+    // read jslot, so thread 0 may overwrite jslot at the next iteration.
   }
 }
 

@@ -250,6 +250,10 @@ __device__ __forceinline__ void dma_stage(__amdgpu_buffer_rsrc_t ra, __amdgpu_bu
 }
 
 // Compute tile (yt, xt) and write its strict-upper-triangle pairs.
+// The last stage copy of a call may still be in flight when it returns (it
+// fills LDS units that the same wave fills first at the next call with the
+// same TILE); a workgroup that switches TILE between calls waits for its
+// outstanding loads (vmcnt(0)) before the next call.
 // Requires: all 512 threads of the workgroup call it together; smem holds
 // TileShape<TILE>::LDS_UNITS units; rows yt*TILE .. +TILE and xt*TILE .. +TILE
 // exist in Z (n_pad is a multiple of 256); TILE * row_bytes <= 2^32.
@@ -298,23 +302,41 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
   __syncthreads();
   read_half<MODE, NBR>(smem + aoff, i, g, 0, f0a);
   read_half<MODE, NBC>(smem + boff, i, g, 0, f0b);
-  for (int c = 0; c < nch; ++c) {
+  // Every stage but the last.  The last one is peeled off below, so the
+  // loop body has a single path: were the barrier conditional, the compiler
+  // would merge a path with the second-half reads still in flight into the
+  // one without, and make the second-half MFMAs wait for the next stage's
+  // first-half reads issued right after the barrier.
+  for (int c = 0; c + 1 < nch; ++c) {
     const u32x4 *cur = smem + (c & 1) * 2 * OPU;
     read_half<MODE, NBR>(cur + aoff, i, g, 1, f1a);
     read_half<MODE, NBC>(cur + boff, i, g, 1, f1b);
     mfma_half<MODE, NBR, NBC>(f0a, f0b, acc);
-    if (c + 1 < nch) {
-      // own DMA of stage c+1 landed and own reads of stage c returned; the
-      // barrier makes both true for every wave
-      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
-      __syncthreads();
-      const u32x4 *nxt = smem + ((c + 1) & 1) * 2 * OPU;
-      read_half<MODE, NBR>(nxt + aoff, i, g, 0, f0a);
-      read_half<MODE, NBC>(nxt + boff, i, g, 0, f0b);
-      if (c + 2 < nch)
-        dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8,
-                        (uint32_t)(c + 2) * 128u, smem + (c & 1) * 2 * OPU, w);
+    // own DMA of stage c+1 landed and own reads of stage c returned; the
+    // barrier makes both true for every wave
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __syncthreads();
+    const u32x4 *nxt = smem + ((c + 1) & 1) * 2 * OPU;
+    read_half<MODE, NBR>(nxt + aoff, i, g, 0, f0a);
+    read_half<MODE, NBC>(nxt + boff, i, g, 0, f0b);
+    // Stage c + 2 into the buffer stage c used.  Issued unconditionally (the
+    // last stage is loaded again when c + 2 == nch, into a buffer nobody
+    // reads any more), so the loads sit in the same block as the MFMAs and
+    // the scheduler interleaves them.  A wave's DMA always fills the same
+    // LDS units and its loads complete in order, so that extra load lands
+    // before the next tile's first stage overwrites the buffer.
+    {
+      const int cn = (c + 2 < nch) ? c + 2 : nch - 1;
+      dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8, (uint32_t)cn * 128u,
+                      smem + (c & 1) * 2 * OPU, w);
     }
+    mfma_half<MODE, NBR, NBC>(f1a, f1b, acc);
+  }
+  {
+    const u32x4 *cur = smem + ((nch - 1) & 1) * 2 * OPU;
+    read_half<MODE, NBR>(cur + aoff, i, g, 1, f1a);
+    read_half<MODE, NBC>(cur + boff, i, g, 1, f1b);
+    mfma_half<MODE, NBR, NBC>(f0a, f0b, acc);
     mfma_half<MODE, NBR, NBC>(f1a, f1b, acc);
   }
 
