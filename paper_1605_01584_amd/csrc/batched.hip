@@ -34,21 +34,51 @@ struct BatchDesc {
   int64_t m;     // tiles per side
   int64_t job0;  // first job id of this dataset in the concatenated space
   int64_t row0;  // first padded row of this dataset in the concatenated rows
+  int64_t grp0;  // first row group (64 / lanes rows, one wave) of this dataset
   int32_t xt;
   int32_t tile;
   int32_t nchunks;
+  int32_t lanes;  // lanes per row in the transformation (16, 32 or 64)
   float scale;
   double out_scale;  // normalisation multiplier (FP16 layout: sqrt(l))
 };
 
 constexpr size_t kCounterBytes = 256;
+constexpr int kCounterStride = 16;  // the two job counters, 128 bytes apart
+constexpr int kBatchCacheSamples = 32;  // input samples cached per lane
 
-__device__ __forceinline__ int find_desc(const BatchDesc *d, int D, int64_t key, bool by_job) {
-  int lo = 0, hi = D - 1;  // last dataset whose start <= key
+// Workspace: [job counters | descriptor table | job0 of every dataset |
+// first row group of every dataset], each part 256-byte aligned.  A
+// workgroup copies the start keys it searches (first job or first row group
+// of each dataset) into LDS when there are at most kKeysInLds datasets, so
+// that finding the dataset of
+// a job or a row is a binary search in LDS instead of a chain of dependent
+// global loads; larger batches search the compact key array in place.
+constexpr int kKeysInLds = 1024;
+
+inline size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Whole workgroup; returns the keys to search (LDS copy or global array).
+__device__ __forceinline__ const int64_t *load_keys(const int64_t *__restrict__ gkeys, int D,
+                                                    int64_t *skeys) {
+  if (D > kKeysInLds) return gkeys;
+  for (int i = threadIdx.x; i < D; i += blockDim.x) skeys[i] = gkeys[i];
+  __syncthreads();
+  return skeys;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Last dataset whose start key <= key.
+__device__ __forceinline__ int find_desc(const int64_t *keys, int D, int64_t key) {
+  int lo = 0, hi = D - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int64_t start = by_job ? d[mid].job0 : d[mid].row0;
-    if (start <= key)
+    if (keys[mid] <= key)
       lo = mid;
     else
       hi = mid - 1;
@@ -56,81 +86,128 @@ __device__ __forceinline__ int find_desc(const BatchDesc *d, int D, int64_t key,
   return lo;
 }
 
-__global__ void batch_zero_kernel(unsigned long long *counter) { *counter = 0ull; }
+__global__ void batch_zero_kernel(unsigned long long *counters) {
+  counters[0] = 0ull;
+  counters[kCounterStride] = 0ull;
+}
+
+// Row normalisation of a batch.  One kernel serves every input variant of
+// the batch (FP32/FP64, vector or scalar loads), so it caches 32 samples per
+// lane in every mode to keep the four inlined variants within two waves per
+// SIMD.  A row is owned by `lanes` lanes: short rows share a wave (16 or 32
+// lanes each), so a wave has several rows' loads in flight at once.
+template <typename TIn, int MODE, bool VEC>
+__device__ __forceinline__ void batch_row(const TIn *xr, int64_t l, int64_t l_pad,
+                                          unsigned char *zr, double out_scale, int lanes) {
+  normalize_row<TIn, MODE, kBatchCacheSamples / UnitOf<MODE>::E, VEC>(
+      xr, l, l_pad, zr, nullptr, nullptr, out_scale, lanes);
+}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_norm_kernel(const BatchDesc *__restrict__ descs,
-                                                         int D, int64_t total_rows) {
+                                                         const int64_t *__restrict__ grp0s, int D,
+                                                         int64_t total_groups) {
+  __shared__ int64_t skeys[kKeysInLds];
+  const int64_t *keys = load_keys(grp0s, D, skeys);
   const int64_t stride = (int64_t)gridDim.x * 4;
-  for (int64_t R = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); R < total_rows; R += stride) {
-    const BatchDesc &d = descs[find_desc(descs, D, R, false)];
-    const int64_t row = R - d.row0;
+  // one row group per wave: the group and its dataset are wave-uniform,
+  // which keeps the descriptor in scalar registers
+  for (int64_t W = uniform64((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)); W < total_groups;
+       W += stride) {
+    const BatchDesc &d = descs[__builtin_amdgcn_readfirstlane(find_desc(keys, D, W))];
+    const int lanes = d.lanes;
+    const int64_t row = (W - d.grp0) * (64 / lanes) + (int64_t)((threadIdx.x & 63) / lanes);
     unsigned char *zr = d.z + row * d.row_bytes;
     if (row >= d.n) {
-      zero_row(zr, d.row_bytes);
+      zero_row(zr, d.row_bytes, lanes);
       continue;
     }
     if (d.xt == PCC_IN_F64) {
       const double *xr = (const double *)d.x + row * d.ldx;
       const bool vec = (d.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
-      normalize_row<double, MODE, CacheOf<MODE>::C>(xr, d.l, d.l_pad, zr, nullptr, nullptr,
-                                                    d.out_scale, vec);
+      if (vec)
+        batch_row<double, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+      else
+        batch_row<double, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
     } else {
       const float *xr = (const float *)d.x + row * d.ldx;
       const bool vec = (d.ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
-      normalize_row<float, MODE, CacheOf<MODE>::C>(xr, d.l, d.l_pad, zr, nullptr, nullptr,
-                                                   d.out_scale, vec);
+      if (vec)
+        batch_row<float, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+      else
+        batch_row<float, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
     }
   }
 }
 
-template <int MODE>
+// All-pairs jobs of the datasets that use one tile size: tile ids drawn
+// from a device counter over the datasets' concatenated job spaces.
+template <int MODE, int TILE>
 __global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const BatchDesc *__restrict__ descs,
+                                                            const int64_t *__restrict__ job0s,
                                                             int D, int64_t total_jobs,
                                                             unsigned long long *counter) {
-  __shared__ u32x4 smem[TileShape<256>::LDS_UNITS];
+  __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
   __shared__ int64_t jslot;
+  __shared__ int64_t skeys[kKeysInLds];
+  const int64_t *keys = load_keys(job0s, D, skeys);
   for (;;) {
     if (threadIdx.x == 0) jslot = (int64_t)atomicAdd(counter, 1ull);
     __syncthreads();
-    const int64_t J = jslot;
-    if (J >= total_jobs) break;  // uniform across the workgroup
-    const BatchDesc &d = descs[find_desc(descs, D, J, true)];
+    // J and the dataset index are uniform across the workgroup; saying so
+    // keeps the descriptor in scalar registers
+    const int64_t J = uniform64(jslot);
+    if (J >= total_jobs) break;
+    const BatchDesc &d = descs[__builtin_amdgcn_readfirstlane(find_desc(keys, D, J))];
     const Cell tc = tri_cell(d.m, J - d.job0);
     ZView zv{d.z, d.row_bytes, d.n, d.nchunks, d.scale, d.z, d.n};
     EpiArgs ea{};
     ea.r = d.r;
-    // Consecutive jobs may use different tile sizes, whose stage copies give
-    // a wave different LDS units: the previous job's last copies (possibly
-    // still in flight) must land before any wave starts the next job's.
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (d.tile == 128)
-      do_tile<MODE, 128, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
-    else
-      do_tile<MODE, 256, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+    do_tile<MODE, TILE, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
     // do_tile begins with a barrier, which every thread reaches after it has
     // read jslot, so thread 0 may overwrite jslot at the next iteration.
   }
 }
 
-template <int MODE>
-hipError_t launch_batch(const BatchDesc *descs, int D, int64_t total_rows, int64_t total_jobs,
+template <int MODE, int TILE>
+hipError_t launch_tiles(const BatchDesc *descs, const int64_t *job0s, int D, int64_t jobs,
                         unsigned long long *counter, int cus, hipStream_t st) {
-  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(1), 0, st, counter);
+  if (D <= 0 || jobs <= 0) return hipSuccess;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_tile_kernel<MODE, TILE>,
+                                                   kTileThreads, 0) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  int64_t grid = (int64_t)cus * occ;
+  if (grid > jobs) grid = jobs;
+  hipLaunchKernelGGL((batch_tile_kernel<MODE, TILE>), dim3((unsigned)grid), dim3(kTileThreads), 0,
+                     st, descs, job0s, D, jobs, counter);
+  return hipGetLastError();
+}
+
+// descs[0, d256) use 256-wide tiles (jobs256 jobs, counters[0]), the rest
+// 128-wide (jobs128 jobs, counters[kCounterStride]); job0 restarts at 0 in
+// each group.
+
+template <int MODE>
+hipError_t launch_batch(const BatchDesc *descs, const int64_t *job0s, const int64_t *grp0s, int D,
+                        int d256, int64_t total_groups, int64_t jobs256, int64_t jobs128,
+                        unsigned long long *counters, int cus, hipStream_t st) {
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(1), 0, st, counters);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int64_t nblocks = (total_rows + 3) / 4;
-  if (nblocks > 65536) nblocks = 65536;
+  // grid-stride over row groups: a few workgroups per compute unit, each
+  // loading the key table once
+  int64_t nblocks = (total_groups + 3) / 4;
+  if (nblocks > (int64_t)cus * 8) nblocks = (int64_t)cus * 8;
   hipLaunchKernelGGL((batch_norm_kernel<MODE>), dim3((unsigned)nblocks), dim3(256), 0, st, descs,
-                     D, total_rows);
+                     grp0s, D, total_groups);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int64_t grid = cus;
-  if (grid > total_jobs) grid = total_jobs;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((batch_tile_kernel<MODE>), dim3((unsigned)grid), dim3(kTileThreads), 0, st, descs, D,
-                     total_jobs, counter);
-  return hipGetLastError();
+  e = launch_tiles<MODE, 256>(descs, job0s, d256, jobs256, counters, cus, st);
+  if (e != hipSuccess) return e;
+  return launch_tiles<MODE, 128>(descs + d256, job0s + d256, D - d256, jobs128,
+                                 counters + kCounterStride, cus, st);
 }
 
 }  // namespace
@@ -151,7 +228,8 @@ extern "C" {
 
 size_t pcc_batch_workspace_size(int32_t D) {
   if (D < 0) return 0;
-  return kCounterBytes + ((size_t)D * sizeof(BatchDesc) + 255) / 256 * 256;
+  return kCounterBytes + round256((size_t)D * sizeof(BatchDesc)) +
+         2 * round256((size_t)D * sizeof(int64_t));
 }
 
 pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mode_t mode,
@@ -192,24 +270,44 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
     d.xt = it.xt;
     d.tile = tile;
     d.nchunks = (int32_t)(zd.l_pad / zd.kchunk);
+    d.lanes = norm_lanes(zd.l_pad);
     d.scale = (mode == PCC_FP16) ? (float)(1.0 / (double)zd.l) : 1.0f;
     d.out_scale = (mode == PCC_FP16) ? sqrt((double)zd.l) : 1.0;
   }
-  // Longest jobs first (work of one job ~ tile^2 * l_pad).
+  // 256-wide datasets first, then 128-wide ones (one kernel each); longest
+  // jobs first within a group (work of one job ~ l_pad for a given tile).
   std::stable_sort(ds.begin(), ds.end(), [](const BatchDesc &a, const BatchDesc &b) {
-    return (double)a.tile * a.tile * a.l_pad > (double)b.tile * b.tile * b.l_pad;
+    if (a.tile != b.tile) return a.tile > b.tile;
+    return a.l_pad > b.l_pad;
   });
-  int64_t jobs = 0, rows = 0;
+  int64_t jobs256 = 0, jobs128 = 0, rows = 0, groups = 0;
+  int d256 = 0;
   for (BatchDesc &d : ds) {
+    int64_t &jobs = (d.tile == 256) ? jobs256 : jobs128;
+    if (d.tile == 256) ++d256;
     d.job0 = jobs;
     d.row0 = rows;
+    d.grp0 = groups;
     jobs += d.m * (d.m + 1) / 2;
     rows += d.n_pad;
+    groups += d.n_pad / (64 / d.lanes);  // n_pad is a multiple of 256
   }
+  const int64_t jobs = jobs256 + jobs128;
   hipStream_t st = (hipStream_t)stream;
   unsigned char *ws = (unsigned char *)workspace;
   BatchDesc *ddesc = (BatchDesc *)(ws + kCounterBytes);
+  int64_t *djob0 = (int64_t *)(ws + kCounterBytes + round256((size_t)D * sizeof(BatchDesc)));
+  int64_t *dgrp0 = (int64_t *)((unsigned char *)djob0 + round256((size_t)D * sizeof(int64_t)));
+  std::vector<int64_t> keys(2 * (size_t)D);
+  for (int32_t k = 0; k < D; ++k) {
+    keys[(size_t)k] = ds[(size_t)k].job0;
+    keys[(size_t)D + k] = ds[(size_t)k].grp0;
+  }
   if (note_hip(hipMemcpyAsync(ddesc, ds.data(), ds.size() * sizeof(BatchDesc),
+                              hipMemcpyHostToDevice, st)) != hipSuccess ||
+      note_hip(hipMemcpyAsync(djob0, keys.data(), (size_t)D * sizeof(int64_t),
+                              hipMemcpyHostToDevice, st)) != hipSuccess ||
+      note_hip(hipMemcpyAsync(dgrp0, keys.data() + D, (size_t)D * sizeof(int64_t),
                               hipMemcpyHostToDevice, st)) != hipSuccess ||
       note_hip(hipStreamSynchronize(st)) != hipSuccess)
     return PCC_E_HIP;
@@ -237,12 +335,12 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
     unsigned long long *counter = (unsigned long long *)ws;
     hipError_t e = hipErrorInvalidValue;
     switch (mode) {
-      case PCC_FP32: e = launch_batch<PCC_FP32>(ddesc, D, rows, jobs, counter, cus, cs); break;
+      case PCC_FP32: e = launch_batch<PCC_FP32>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
       case PCC_SPLIT_BF16X3:
-        e = launch_batch<PCC_SPLIT_BF16X3>(ddesc, D, rows, jobs, counter, cus, cs);
+        e = launch_batch<PCC_SPLIT_BF16X3>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs);
         break;
-      case PCC_BF16: e = launch_batch<PCC_BF16>(ddesc, D, rows, jobs, counter, cus, cs); break;
-      case PCC_FP16: e = launch_batch<PCC_FP16>(ddesc, D, rows, jobs, counter, cus, cs); break;
+      case PCC_BF16: e = launch_batch<PCC_BF16>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
+      case PCC_FP16: e = launch_batch<PCC_FP16>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
     }
     hipGraph_t g = nullptr;
     note_hip(e);

@@ -2,7 +2,8 @@
 // single-matrix kernel (normalize.hip) and the uneven-batch kernel
 // (batched.hip).
 //
-// One 64-lane wave owns one row.  The row is read once from HBM with
+// A group of G lanes (16, 32 or 64: a whole wave by default, several short
+// rows per wave in a batch) owns one row.  The row is read once from HBM with
 // coalesced 16-byte loads, kept in registers in its input type (units of 4
 // or 8 consecutive samples per lane, up to kCache units per lane; longer rows
 // are re-read, from L2, by the later passes), and reduced across the wave in
@@ -22,9 +23,10 @@
 
 namespace pcc {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sum over the G lanes of a group (G a power of two dividing 64; every lane
+// of the group takes part).
+__device__ __forceinline__ double group_sum(double v, int G) {
+  for (int off = G >> 1; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
@@ -33,14 +35,18 @@ template <int MODE> struct UnitOf {
   static constexpr int E = (MODE == PCC_FP64) ? 2 : ((MODE == PCC_FP32) ? 4 : 8);
 };
 
-// Input samples cached in registers per lane (32: rows up to 2048 samples
-// are read from HBM exactly once).
-template <int MODE> struct CacheOf { static constexpr int C = 32 / UnitOf<MODE>::E; };
+// Input units cached in registers per lane: 32 samples (rows up to 2048
+// samples are read from HBM exactly once), 64 for FP32 output from FP32
+// input (rows up to 4096; that variant has the registers to spare).  Longer
+// rows re-read the rest in the later passes.
+template <typename TIn, int MODE> struct CacheOf {
+  static constexpr int C =
+      ((MODE == PCC_FP32 && sizeof(TIn) == 4) ? 64 : 32) / UnitOf<MODE>::E;
+};
 
-template <typename TIn, int E>
-__device__ __forceinline__ void load_unit(const TIn *row, int64_t l, int64_t k0, bool vec,
-                                          TIn (&v)[E]) {
-  if (vec && k0 + E <= l) {
+template <typename TIn, int E, bool VEC>
+__device__ __forceinline__ void load_unit(const TIn *row, int64_t l, int64_t k0, TIn (&v)[E]) {
+  if (VEC && k0 + E <= l) {
     if constexpr (sizeof(TIn) == 4 && E == 2) {
       const float2 f = *reinterpret_cast<const float2 *>(row + k0);
       v[0] = f.x; v[1] = f.y;
@@ -109,38 +115,42 @@ __device__ __forceinline__ void store_unit(unsigned char *zr, int64_t u, const d
   }
 }
 
-// Transform row `row` (< n) of x into row zr of Z.  Called by a whole wave.
-template <typename TIn, int MODE, int kCache>
+// Transform row `row` (< n) of x into row zr of Z.  Called by the G lanes
+// of a group (G = 64: a whole wave).
+// VEC: the row starts 16-byte aligned and a unit of E samples can be read
+// with 16-byte loads (the caller checks the pointer and the pitch).
+template <typename TIn, int MODE, int kCache, bool VEC>
 __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_t l, int64_t l_pad,
                                               unsigned char *__restrict__ zr, double *stats_row,
-                                              int32_t *n_degenerate, double out_scale, bool vec_ok) {
+                                              int32_t *n_degenerate, double out_scale,
+                                              int G = 64) {
   constexpr int E = UnitOf<MODE>::E;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & (G - 1);
   const int64_t units = l_pad / E;
   TIn cache[kCache][E];  // the row stays in registers in its input type
   // pass 1: sum
   double s = 0.0;
 #pragma unroll
   for (int c = 0; c < kCache; ++c) {
-    const int64_t u = lane + 64 * c;
+    const int64_t u = lane + G * c;
     if (u < units) {
-      load_unit<TIn, E>(xr, l, u * E, vec_ok, cache[c]);
+      load_unit<TIn, E, VEC>(xr, l, u * E, cache[c]);
 #pragma unroll
       for (int e = 0; e < E; ++e) s += (double)cache[c][e];
     }
   }
-  for (int64_t u = lane + 64 * kCache; u < units; u += 64) {
+  for (int64_t u = lane + (int64_t)G * kCache; u < units; u += G) {
     TIn v[E];
-    load_unit<TIn, E>(xr, l, u * E, vec_ok, v);
+    load_unit<TIn, E, VEC>(xr, l, u * E, v);
 #pragma unroll
     for (int e = 0; e < E; ++e) s += (double)v[e];
   }
-  const double mean = wave_sum(s) / (double)l;
+  const double mean = group_sum(s, G) / (double)l;
   // pass 2: sum of squared deviations (padding samples excluded)
   double q = 0.0;
 #pragma unroll
   for (int c = 0; c < kCache; ++c) {
-    const int64_t u = lane + 64 * c;
+    const int64_t u = lane + G * c;
     if (u < units) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -149,16 +159,16 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
       }
     }
   }
-  for (int64_t u = lane + 64 * kCache; u < units; u += 64) {
+  for (int64_t u = lane + (int64_t)G * kCache; u < units; u += G) {
     TIn v[E];
-    load_unit<TIn, E>(xr, l, u * E, vec_ok, v);
+    load_unit<TIn, E, VEC>(xr, l, u * E, v);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const double d = (double)v[e] - mean;
       q += (u * E + e < l) ? d * d : 0.0;
     }
   }
-  const double m2 = wave_sum(q);
+  const double m2 = group_sum(q, G);
   const bool degenerate = !(m2 > 0.0) || !(m2 < INFINITY);
   if (lane == 0) {
     if (stats_row) {
@@ -171,7 +181,7 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
   // pass 3: transformed samples, zero padding
 #pragma unroll
   for (int c = 0; c < kCache; ++c) {
-    const int64_t u = lane + 64 * c;
+    const int64_t u = lane + G * c;
     if (u < units) {
       double o[E];
 #pragma unroll
@@ -180,10 +190,10 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
       store_unit<MODE, E>(zr, u, o);
     }
   }
-  for (int64_t u = lane + 64 * kCache; u < units; u += 64) {
+  for (int64_t u = lane + (int64_t)G * kCache; u < units; u += G) {
     TIn v[E];
     double o[E];
-    load_unit<TIn, E>(xr, l, u * E, vec_ok, v);
+    load_unit<TIn, E, VEC>(xr, l, u * E, v);
 #pragma unroll
     for (int e = 0; e < E; ++e) o[e] = (u * E + e < l) ? ((double)v[e] - mean) * inv : 0.0;
     store_unit<MODE, E>(zr, u, o);
@@ -191,9 +201,10 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
 }
 
 // Zero one padding row of Z (rows n .. n_pad-1).
-__device__ __forceinline__ void zero_row(unsigned char *__restrict__ zr, int64_t row_bytes) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t u = lane; u < row_bytes / 16; u += 64)
+__device__ __forceinline__ void zero_row(unsigned char *__restrict__ zr, int64_t row_bytes,
+                                         int G = 64) {
+  const int lane = threadIdx.x & (G - 1);
+  for (int64_t u = lane; u < row_bytes / 16; u += G)
     *reinterpret_cast<uint4 *>(zr + u * 16) = make_uint4(0u, 0u, 0u, 0u);
 }
 

@@ -10,22 +10,26 @@ namespace {
 
 constexpr int kWaves = 4;  // waves (rows) per workgroup
 
-template <typename TIn, int MODE>
+// Wave w of the grid-stride loop owns row group w: rows w * (64 / lanes) ..,
+// one row per `lanes` lanes.
+template <typename TIn, int MODE, bool VEC>
 __global__ __launch_bounds__(64 * kWaves) void normalize_kernel(
     const TIn *__restrict__ x, int64_t ldx, int64_t n, int64_t l, int64_t n_pad, int64_t l_pad,
     int64_t row_bytes, unsigned char *__restrict__ z, double *__restrict__ stats,
-    int32_t *__restrict__ n_degenerate, double out_scale, int vec_ok) {
+    int32_t *__restrict__ n_degenerate, double out_scale, int lanes) {
+  const int64_t rpw = 64 / lanes;
+  const int64_t groups = n_pad / rpw;
   const int64_t stride = (int64_t)gridDim.x * kWaves;
-  for (int64_t row = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); row < n_pad;
-       row += stride) {
+  for (int64_t w = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); w < groups; w += stride) {
+    const int64_t row = w * rpw + (threadIdx.x & 63) / lanes;
     unsigned char *zr = z + row * row_bytes;
     if (row >= n) {
-      zero_row(zr, row_bytes);
+      zero_row(zr, row_bytes, lanes);
       continue;
     }
-    normalize_row<TIn, MODE, CacheOf<MODE>::C>(x + row * ldx, l, l_pad, zr,
-                                              stats ? stats + 2 * row : nullptr, n_degenerate,
-                                              out_scale, vec_ok != 0);
+    normalize_row<TIn, MODE, CacheOf<TIn, MODE>::C, VEC>(x + row * ldx, l, l_pad, zr,
+                                                         stats ? stats + 2 * row : nullptr,
+                                                         n_degenerate, out_scale, lanes);
   }
 }
 
@@ -37,11 +41,18 @@ hipError_t launch_norm(const TIn *x, int64_t ldx, const pcc_zdesc &zd, void *z, 
   const bool vec = ((ldx * (int64_t)sizeof(TIn)) % 16 == 0) &&
                    ((reinterpret_cast<uintptr_t>(x) & 15) == 0);
   const double out_scale = (MODE == PCC_FP16) ? sqrt((double)zd.l) : 1.0;
-  int64_t blocks = (zd.n_pad + kWaves - 1) / kWaves;
+  const int lanes = norm_lanes(zd.l_pad);
+  const int64_t groups = zd.n_pad / (64 / lanes);  // n_pad is a multiple of 256
+  int64_t blocks = (groups + kWaves - 1) / kWaves;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL((normalize_kernel<TIn, MODE>), dim3((unsigned)blocks), dim3(64 * kWaves), 0,
-                     st, x, ldx, zd.n, zd.l, zd.n_pad, zd.l_pad, zd.row_bytes, (unsigned char *)z,
-                     stats, ndeg, out_scale, vec ? 1 : 0);
+  if (vec)
+    hipLaunchKernelGGL((normalize_kernel<TIn, MODE, true>), dim3((unsigned)blocks),
+                       dim3(64 * kWaves), 0, st, x, ldx, zd.n, zd.l, zd.n_pad, zd.l_pad,
+                       zd.row_bytes, (unsigned char *)z, stats, ndeg, out_scale, lanes);
+  else
+    hipLaunchKernelGGL((normalize_kernel<TIn, MODE, false>), dim3((unsigned)blocks),
+                       dim3(64 * kWaves), 0, st, x, ldx, zd.n, zd.l, zd.n_pad, zd.l_pad,
+                       zd.row_bytes, (unsigned char *)z, stats, ndeg, out_scale, lanes);
   return hipGetLastError();
 }
 
