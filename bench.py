@@ -161,12 +161,18 @@ def main():
     ap.add_argument("--l", type=int, default=4096)
     ap.add_argument("--mode", default="split")
     ap.add_argument("--no-extras", action="store_true", help="headline step only")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of extra legs (normalize, fp32, edges, fp64, xy, to_host, "
+                         "calibration, permtest, batched, big_edges), default all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run a plain 1 GiB device copy (twice) whose "
                          "known traffic calibrates the HBM byte counters")
     args = ap.parse_args()
+
+    def want(leg):
+        return not args.no_extras and (args.legs == "all" or leg in args.legs.split(","))
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the all-pairs path "
                                    "is measured on a single MI355X (multi-GPU sharding is a "
@@ -260,13 +266,14 @@ def main():
     }
 
     extras = {}
-    if not args.no_extras:
+    if want("normalize"):
         # normalisation alone (HBM-bound)
         nm, _ = timed(norm, 5, stream)
         nbytes = n * l * 4 + zd.bytes
         extras["normalize"] = {"ms": nm, "GB_per_s": nbytes / (nm * 1e-3) / 1e9,
                                "hbm_frac": nbytes / (nm * 1e-3) / HBM_PEAK,
                                "bytes": nbytes}
+    if want("fp32"):
         # FP32 path
         zd32 = pcc.z_layout(n, l, "fp32")
         z32 = torch.empty(zd32.bytes, dtype=torch.uint8, device=dev)
@@ -277,6 +284,8 @@ def main():
             "tile_ms": t32, "pair_samples_per_s": pair_samples / (t32 * 1e-3),
             "mfma_frac": 2.0 * pair_samples / (t32 * 1e-3) / PEAK["fp32"],
             "split_speedup_over_fp32": t32 / tile_avg}
+        del z32
+    if want("edges"):
         # edges epilogue (|r| >= 0.8)
         cap = 1 << 20
         ij = torch.empty((cap, 2), dtype=torch.int32, device=dev)
@@ -294,8 +303,8 @@ def main():
         te, _ = timed(edges, 3, stream)
         extras["edges"] = {"ms": te, "threshold": 0.8, "count": int(cnt.item()),
                            "pair_samples_per_s": pair_samples / (te * 1e-3)}
-        del z32
         del ij, rv
+    if want("fp64"):
         # FP64 tiles (the paper's precision), FP64 output
         log("[bench] FP64 tile path")
         zd64 = pcc.z_layout(n, l, "fp64")
@@ -311,6 +320,7 @@ def main():
             "tile": cfg64.tile}
         del z64, r64
         torch.cuda.empty_cache()
+    if want("xy"):
         # non-symmetric all pairs: the two halves of X against each other
         log("[bench] non-symmetric X x Y")
         h = n // 2
@@ -327,6 +337,7 @@ def main():
                         "mfma_frac": 2.0 * MFMA_PER_MAC[mode] * ps_xy / (txy * 1e-3) / PEAK[dt]}
         del zx, zy, rxy
         torch.cuda.empty_cache()
+    if want("to_host"):
         # multi-pass all pairs into pinned host memory (8 tile rows per pass)
         log("[bench] multi-pass to host")
         host = torch.empty(npairs, dtype=torch.float32, pin_memory=True)
@@ -358,6 +369,7 @@ def main():
             "compute_only_ms": tile_avg}
         del host, dev_buf
         torch.cuda.empty_cache()
+    if want("calibration"):
         log("[bench] calibration: MFMA loop, device copy, hipBLASLt GEMM")
         extras["calibration"] = calibration(dev, stream)
 
@@ -392,11 +404,13 @@ def main():
     else:
         out["cpu_baseline"] = None
 
-    if not args.no_extras:
-        del r
-        torch.cuda.empty_cache()
+    del r
+    torch.cuda.empty_cache()
+    if want("permtest"):
         extras.update(bench_permtest(pcc, workloads, stream, dev))
+    if want("batched"):
         extras.update(bench_batched(pcc, workloads, stream, dev))
+    if want("big_edges"):
         extras.update(bench_big_edges(pcc, workloads, stream, dev))
     out["extras"] = extras
     print(json.dumps(out), flush=True)
