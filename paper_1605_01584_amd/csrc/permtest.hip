@@ -52,33 +52,44 @@ size_t lds_bytes(int64_t l_pad) {
   return a + b + (size_t)kBlk * kBlk * 4;
 }
 
-// Four permutation indices of samples k0..k0+3 for permutation p (p < 0:
-// identity).  Samples at or beyond l are padding: they keep their index
-// (their A value is zero, B value zero).
+// Permutation indices of samples k0..k0+3 for the permutation whose row is
+// `row`, in two steps.  perm_load reads them branch-free (the address is
+// clamped into the row), so the loads stay in the MFMA block instead of
+// being fenced by divergent branches; perm_fix then gives samples at or
+// beyond l (padding: A and B are zero there) their own index, exactly as
+// the identity does.
 template <bool ALIGNED>
-__device__ __forceinline__ i32x4 perm_idx(const int32_t *__restrict__ perms, int p, int64_t l,
-                                          int k0) {
-  i32x4 r = {k0, k0 + 1, k0 + 2, k0 + 3};
-  if (p < 0) return r;
-  const int32_t *row = perms + (int64_t)p * l;
+__device__ __forceinline__ i32x4 perm_load(const int32_t *__restrict__ row, int64_t l, int k0) {
   if constexpr (ALIGNED) {  // l % 4 == 0: a group is wholly inside or outside
-    if (k0 < l) r = *reinterpret_cast<const i32x4 *>(row + k0);
+    return *reinterpret_cast<const i32x4 *>(row + (k0 < l ? k0 : 0));
   } else {
+    i32x4 r;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (k0 + e < l) r[e] = row[k0 + e];
+    for (int e = 0; e < 4; ++e) r[e] = row[k0 + e < l ? k0 + e : 0];
+    return r;
   }
+}
+
+__device__ __forceinline__ i32x4 perm_fix(i32x4 raw, int64_t l, int k0) {
+  i32x4 r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) r[e] = (k0 + e < l) ? raw[e] : k0 + e;
   return r;
 }
 
-// One pass of a wave: accumulators for permutations pa and pb over all
-// samples.  Lane (i, g) supplies A[i][k] and B[k][i] for its half's samples
-// k = 8t + 4g + e, e = 0..3, at MFMA step (t, e).
-template <bool ALIGNED>
+// One pass of a wave: accumulators for two permutations (rows ra, rb of the
+// permutation matrix; IDENT_*: the identity instead) over all samples.
+// Lane (i, g) supplies A[i][k] and B[k][i] for its half's samples
+// k = 8t + 4g + e, e = 0..3, at MFMA step (t, e).  The identity gathers
+// through the same LDS read as a permutation, so an identity permutation
+// reproduces the observed r bit for bit.  The indices of step t + 1 are
+// loaded at the start of step t and first used after its MFMAs, so the
+// gathers never wait for a global load issued in the same step.
+template <bool ALIGNED, bool IDENT_A, bool IDENT_B>
 __device__ __forceinline__ void pass2(const float *__restrict__ sA, const float *__restrict__ sB,
-                                      int64_t pa_l, int64_t pb_l, const int32_t *__restrict__ perms,
-                                      int pa, int pb, int64_t l, int nt, int i, int g,
-                                      f32x16 &accA, f32x16 &accB) {
+                                      int64_t pa_l, int64_t pb_l, const int32_t *__restrict__ ra,
+                                      const int32_t *__restrict__ rb, int64_t l, int nt, int i,
+                                      int g, f32x16 &accA, f32x16 &accB) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     accA[v] = 0.0f;
@@ -86,15 +97,32 @@ __device__ __forceinline__ void pass2(const float *__restrict__ sA, const float 
   }
   const float *arow = sA + (int64_t)i * pa_l;
   const float *bcol = sB + (int64_t)i * pb_l;
+  i32x4 na = {}, nb = {};  // raw indices of the next step
+  if constexpr (!IDENT_A) na = perm_load<ALIGNED>(ra, l, 4 * g);
+  if constexpr (!IDENT_B) nb = perm_load<ALIGNED>(rb, l, 4 * g);
   for (int t = 0; t < nt; ++t) {
     const int k0 = 8 * t + 4 * g;
     const f32x4 a = *reinterpret_cast<const f32x4 *>(arow + k0);
-    const i32x4 ia = perm_idx<ALIGNED>(perms, pa, l, k0);
-    const i32x4 ib = perm_idx<ALIGNED>(perms, pb, l, k0);
+    const i32x4 own = {k0, k0 + 1, k0 + 2, k0 + 3};
+    const i32x4 ia = IDENT_A ? own : perm_fix(na, l, k0);
+    const i32x4 ib = IDENT_B ? own : perm_fix(nb, l, k0);
+    const int kn = (t + 1 < nt) ? k0 + 8 : k0;  // the last step reloads its own
+    if constexpr (!IDENT_A) na = perm_load<ALIGNED>(ra, l, kn);
+    if constexpr (!IDENT_B) nb = perm_load<ALIGNED>(rb, l, kn);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       accA = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], bcol[ia[e]], accA, 0, 0, 0);
       accB = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], bcol[ib[e]], accB, 0, 0, 0);
+    }
+    if constexpr (!IDENT_A || !IDENT_B) {
+      // the index loads first in the block, then the gathers and the MFMAs;
+      // the loaded values are first used here, after the MFMAs (an empty asm,
+      // no load in it), so the wait for them falls at the end of the step
+      __builtin_amdgcn_sched_group_barrier(0x020, (IDENT_A || IDENT_B) ? 1 : 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 9, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+      __builtin_amdgcn_sched_barrier(0);  // nothing moves across: the asm stays last
+      asm volatile("" : "+v"(na), "+v"(nb));
     }
   }
 }
@@ -139,22 +167,28 @@ __global__ __launch_bounds__(kThreads, 1) void permtest_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) cnt[v] = 0;
     {
-      const int p0 = w < P ? w : -1;
-      pass2<ALIGNED>(sA, sB, pa_l, pb_l, perms, -1, p0, l, nt, i, g, accA, accB);
+      if (w < P)
+        pass2<ALIGNED, true, false>(sA, sB, pa_l, pb_l, perms, perms + (int64_t)w * l, l, nt, i,
+                                    g, accA, accB);
+      else
+        pass2<ALIGNED, true, true>(sA, sB, pa_l, pb_l, perms, perms, l, nt, i, g, accA, accB);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         robs[v] = fabsf(clamp_unit(accA[v]));
-        if (p0 >= 0) cnt[v] += (fabsf(clamp_unit(accB[v])) >= robs[v]) ? 1 : 0;
+        if (w < P) cnt[v] += (fabsf(clamp_unit(accB[v])) >= robs[v]) ? 1 : 0;
       }
     }
     for (int p = w + kWaves; p < P; p += 2 * kWaves) {
+      // the second permutation of the last pass may not exist: the pass then
+      // repeats the first one and its result is not counted
       const int p2 = p + kWaves;
-      const int pb = p2 < P ? p2 : -1;
-      pass2<ALIGNED>(sA, sB, pa_l, pb_l, perms, p, pb, l, nt, i, g, accA, accB);
+      const bool two = p2 < P;
+      pass2<ALIGNED, false, false>(sA, sB, pa_l, pb_l, perms + (int64_t)p * l,
+                                   perms + (int64_t)(two ? p2 : p) * l, l, nt, i, g, accA, accB);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         cnt[v] += (fabsf(clamp_unit(accA[v])) >= robs[v]) ? 1 : 0;
-        if (pb >= 0) cnt[v] += (fabsf(clamp_unit(accB[v])) >= robs[v]) ? 1 : 0;
+        if (two) cnt[v] += (fabsf(clamp_unit(accB[v])) >= robs[v]) ? 1 : 0;
       }
     }
     // accumulator register v of lane (i, g): row 8(v/4) + 4g + v%4, column i
