@@ -204,3 +204,33 @@ def test_config2_expression_fp32():
     err = np.abs(got - ref)
     print(f"config2 fp32: max|dr| over {len(I)} pairs = {err.max():.3e}")
     assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["fp32", "split", "fp64"])
+def test_longest_rows(mode):
+    """l = 2^21, the largest the layout accepts: a panel of the row-padded Z
+    (256 rows, or 128 in FP64) is exactly 2 GiB and every tile load offset
+    stays within 32 bits.  Three profiles, one tile job of 65536 stages."""
+    import torch
+    import paper_1605_01584_amd as pcc
+    l = 1 << 21
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((3, l)).astype(np.float32)
+    X[2] = 0.6 * X[0] + 0.8 * X[2]                     # r(0, 2) near 0.6
+    zd = pcc.z_layout(3, l, mode)
+    assert (128 if mode == "fp64" else 256) * zd.row_bytes == 1 << 31
+    z, zd = pcc.normalize(to_device(X), mode)
+    r = pcc.allpairs_f64(z, zd) if mode == "fp64" else pcc.allpairs(z, zd)
+    torch.cuda.synchronize()
+    ref = oracle.pearson_packed(X)
+    got = r.cpu().numpy().astype(np.float64)
+    # An FP32 accumulator takes l / K rounded MFMA updates (K = 2 for FP32,
+    # 16 for BF16); their rounding errors grow like the square root of that
+    # count: about sqrt(l / 2) 2^-24 = 6e-5 here.  The bound checks addressing
+    # (a wrong panel offset gives errors of order 0.1), not the accuracy
+    # target, which is stated for l = 4096.
+    tol = {"fp32": 4 * np.sqrt(l / 2) * 2.0 ** -24, "split": 4 * np.sqrt(l / 2) * 2.0 ** -24,
+           "fp64": (2 * l + 64) * 2.0 ** -53}[mode]
+    assert np.max(np.abs(got - ref)) <= tol, (got, ref)
+    del z, r
+    torch.cuda.empty_cache()
