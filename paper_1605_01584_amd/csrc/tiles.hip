@@ -11,6 +11,8 @@
 // tile ids): workgroup b takes ids s(b), s(b) + G, s(b) + 2G, ..., where s()
 // gives the workgroups of one XCD consecutive ids.  Every job has the same
 // work, so the static stride balances without a counter.
+#include <atomic>
+
 #include "tile_core.h"
 
 namespace pcc {
@@ -132,19 +134,24 @@ hipError_t zero_count(int64_t *count, hipStream_t st) {
 
 }  // namespace
 
+// Workgroups of a tile kernel one compute unit holds, queried once per
+// kernel (calls from several host threads may race to fill an entry; they
+// store the same value, and the entries are atomic).
 int tile_occupancy(int mode, int tile, int epi) {
-  static int cache[5][2][5] = {};
+  static std::atomic<int> cache[5][2][5] = {};
   if (mode < 0 || mode > 4 || epi < 0 || epi > 4) return 1;
-  int &c = cache[mode][tile == 128 ? 0 : 1][epi];
-  if (c == 0) {
+  std::atomic<int> &c = cache[mode][tile == 128 ? 0 : 1][epi];
+  int v = c.load(std::memory_order_relaxed);
+  if (v == 0) {
     int nb = 0;
     const void *k = kernel_for(mode, tile, epi);
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kTileThreads, 0) != hipSuccess ||
         nb < 1)
       nb = 1;
-    c = nb;
+    c.store(nb, std::memory_order_relaxed);
+    v = nb;
   }
-  return c;
+  return v;
 }
 
 hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const pcc_tile_cfg &cfg,

@@ -234,3 +234,42 @@ def test_longest_rows(mode):
     assert np.max(np.abs(got - ref)) <= tol, (got, ref)
     del z, r
     torch.cuda.empty_cache()
+
+
+def test_concurrent_calls_on_distinct_streams():
+    """Calls on distinct streams from several host threads give the same
+    results as sequential calls (the ABI's thread-safety promise)."""
+    import threading
+    import torch
+    import paper_1605_01584_amd as pcc
+    rng = np.random.default_rng(64)
+    Xs = [rng.standard_normal((1500 + 300 * k, 80)).astype(np.float32) for k in range(4)]
+    modes = ["split", "fp32", "split", "fp64"]
+    ref = []
+    for X, m in zip(Xs, modes):
+        z, zd = pcc.normalize(to_device(X), m)
+        ref.append(pcc.allpairs(z, zd).cpu().numpy())
+    out = [None] * len(Xs)
+    errors = []
+
+    def work(k):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                x = to_device(Xs[k])
+                for _ in range(3):
+                    z, zd = pcc.normalize(x, modes[k], stream=st)
+                    r = pcc.allpairs(z, zd, stream=st)
+                st.synchronize()
+                out[k] = r.cpu().numpy()
+        except Exception as e:      # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(len(Xs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for k in range(len(Xs)):
+        assert np.array_equal(out[k], ref[k])
