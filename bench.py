@@ -418,20 +418,31 @@ def main():
 
 def bench_permtest(pcc, workloads, stream, dev):
     import torch
-    log("[bench] permutation test n=8192 l=512 P=1000")
+    log("[bench] permutation test n=8192 l=512 P=1000 (FP32, split)")
     X, _, perms = workloads.config4()
     n, l = X.shape
     P = perms.shape[0]
     x = torch.from_numpy(X).to(dev)
-    z, zd = pcc.normalize(x, "fp32")
     pt = torch.from_numpy(perms).to(dev)
-    counts = torch.empty(n * (n - 1) // 2, dtype=torch.int32, device=dev)
-    pcc.permtest(z, zd, pt[:8], out=counts)   # warm-up with a few permutations
-    ms, _ = timed(lambda: pcc.permtest(z, zd, pt, out=counts), 2, stream)
     ps = (n * (n - 1) // 2) * l * (P + 1)
-    return {"permtest": {"workload": f"n={n} l={l} P={P} FP32 MFMA, one launch", "ms": ms,
-                         "pair_samples_per_s": ps / (ms * 1e-3),
-                         "mfma_frac": 2.0 * ps / (ms * 1e-3) / PEAK["fp32"]}}
+    out, counts = {}, {}
+    for mode, peak, mfmas in (("fp32", PEAK["fp32"], 1), ("split", PEAK["bf16"], 3)):
+        z, zd = pcc.normalize(x, mode)
+        c = torch.empty(n * (n - 1) // 2, dtype=torch.int32, device=dev)
+        pcc.permtest(z, zd, pt[:8], out=c)   # warm-up with a few permutations
+        ms, _ = timed(lambda: pcc.permtest(z, zd, pt, out=c), 2, stream)
+        counts[mode] = c
+        key = "permtest" if mode == "fp32" else "permtest_split"
+        out[key] = {"workload": f"n={n} l={l} P={P} {'FP32' if mode == 'fp32' else 'split-BF16x3'} "
+                                f"MFMA, one launch", "ms": ms,
+                    "pair_samples_per_s": ps / (ms * 1e-3),
+                    "mfma_frac": 2.0 * mfmas * ps / (ms * 1e-3) / peak}
+        del z
+    d = (counts["split"] - counts["fp32"]).abs()
+    out["permtest_split"]["vs_fp32_counts"] = {
+        "equal_frac": float((d == 0).float().mean()), "max_abs_diff": int(d.max()),
+        "speedup": out["permtest"]["ms"] / out["permtest_split"]["ms"]}
+    return out
 
 
 def bench_batched(pcc, workloads, stream, dev):

@@ -248,8 +248,12 @@ pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
  *          LDS contents of the job (never outside the workgroup's LDS), so
  *          its counts are meaningless.  The Python binding checks them.
  *   counts device int32, n(n-1)/2.
- * Supported: mode FP32 (the test compares |r| differences far below the
- * 16-bit modes' error), l_pad <= pcc_permtest_max_l(PCC_FP32). */
+ * Supported modes: FP32 (FP32 MFMA; every r within about 1e-7 of exact) and
+ * split-BF16x3 (three BF16 products per sample, about 5x the FP32 rate; r
+ * within split's 1e-5, so a count can differ from the exact one only in
+ * permutations whose |r| lies that close to |r_obs|).  The plain 16-bit
+ * modes are refused: their r error (1e-4 and more) would decide too many
+ * counts.  l_pad <= pcc_permtest_max_l(mode). */
 pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
                         const int32_t *perms, int32_t P, int32_t *counts,
                         void *workspace, void *stream);

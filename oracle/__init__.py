@@ -44,7 +44,8 @@ def _load():
     lib.oracle_transform.restype = ctypes.c_int
     lib.oracle_edges.argtypes = [_dp, _i64, _i64, _i64, ctypes.c_double, _i64, _lp, _lp, _dp]
     lib.oracle_edges.restype = _i64
-    lib.oracle_permcounts.argtypes = [_dp, _i64, _i64, _i64, _ip, _i32, _lp, _lp, _i64, _ip, _dp]
+    lib.oracle_permcounts.argtypes = [_dp, _i64, _i64, _i64, _ip, _i32, _lp, _lp, _i64, _ip, _dp,
+                                      ctypes.c_double, _ip, _ip]
     lib.oracle_permcounts.restype = ctypes.c_int
     lib.oracle_enumerate_upper.argtypes = [_i64, _i32, _lp, _lp]
     lib.oracle_enumerate_upper.restype = _i64
@@ -140,8 +141,11 @@ def edges(X, thr: float, cap: int = 1 << 20):
     return EI[:cnt].copy(), EJ[:cnt].copy(), ER[:cnt].copy()
 
 
-def permcounts(X, perms, I, J):
-    """(counts int32, gap FP64) of the permutation test on pairs (I, J)."""
+def permcounts(X, perms, I, J, band=None):
+    """(counts int32, gap FP64) of the permutation test on pairs (I, J).
+    With band, also (c_lo, c_hi): the counts of |r_p| >= |r_obs| + band and
+    of |r_p| >= |r_obs| - band, the range a computation whose every |r| is
+    off by less than band/2 can produce."""
     X = _f64(X)
     n, l = X.shape
     perms = np.ascontiguousarray(perms, dtype=np.int32)
@@ -151,12 +155,20 @@ def permcounts(X, perms, I, J):
     J = np.ascontiguousarray(J, dtype=np.int64)
     counts = np.empty(I.shape[0], dtype=np.int32)
     gap = np.empty(I.shape[0], dtype=np.float64)
+    lo = hi = None
+    if band is not None:
+        lo = np.empty(I.shape[0], dtype=np.int32)
+        hi = np.empty(I.shape[0], dtype=np.int32)
     rc = _load().oracle_permcounts(_ptr(X, _dp), n, l, l, _ptr(perms, _ip), perms.shape[0],
                                    _ptr(I, _lp), _ptr(J, _lp), I.shape[0], _ptr(counts, _ip),
-                                   _ptr(gap, _dp))
+                                   _ptr(gap, _dp), float(band or 0.0),
+                                   None if lo is None else _ptr(lo, _ip),
+                                   None if hi is None else _ptr(hi, _ip))
     if rc != 0:
         raise RuntimeError(f"oracle_permcounts: {rc}")
-    return counts, gap
+    if band is None:
+        return counts, gap
+    return counts, gap, lo, hi
 
 
 def enumerate_upper(n: int, diag: bool):

@@ -181,11 +181,14 @@ int64_t oracle_edges(const double *X, int64_t n, int64_t l, int64_t ld,
  * perms holds P permutations of 0..l-1 (row p: position k takes sample
  * perms[p*l + k]).  counts[q] = #{p : |r_p| >= |r_obs|}, or -1 when r_obs is
  * NaN; gap[q] = min_p | |r_p| - |r_obs| | (how close the nearest decision
- * was), NaN when r_obs is NaN. */
+ * was), NaN when r_obs is NaN.  With c_lo and c_hi (nullable), the counts a
+ * computation whose |r| values are each off by less than band/2 can reach:
+ * c_lo[q] = #{p : |r_p| >= |r_obs| + band}, c_hi[q] = #{p : |r_p| >= |r_obs| -
+ * band} (-1 both when r_obs is NaN). */
 int oracle_permcounts(const double *X, int64_t n, int64_t l, int64_t ld,
                       const int32_t *perms, int32_t P, const int64_t *I,
                       const int64_t *J, int64_t np, int32_t *counts,
-                      double *gap) {
+                      double *gap, double band, int32_t *c_lo, int32_t *c_hi) {
   if (!X || !perms || !I || !J || !counts || l < 1 || ld < l || P < 0) return -1;
   for (int64_t q = 0; q < np; ++q)
     if (I[q] < 0 || I[q] >= n || J[q] < 0 || J[q] >= n) return -3;
@@ -208,21 +211,27 @@ int oracle_permcounts(const double *X, int64_t n, int64_t l, int64_t ld,
       if (isnan(robs)) {
         counts[q] = -1;
         if (gap) gap[q] = NAN;
+        if (c_lo) c_lo[q] = -1;
+        if (c_hi) c_hi[q] = -1;
         continue;
       }
       const double aobs = fabs(robs);
-      int32_t c = 0;
+      int32_t c = 0, lo = 0, hi = 0;
       double g = INFINITY;
       for (int32_t p = 0; p < P; ++p) {
         const int32_t *pi = perms + (int64_t)p * l;
         for (int64_t k = 0; k < l; ++k) tmp[k] = v[pi[k]];
         const double ap = fabs(pearson_literal(u, tmp, l));
         if (ap >= aobs) ++c;
+        if (ap >= aobs + band) ++lo;
+        if (ap >= aobs - band) ++hi;
         const double d = fabs(ap - aobs);
         if (d < g) g = d;
       }
       counts[q] = c;
       if (gap) gap[q] = g;
+      if (c_lo) c_lo[q] = lo;
+      if (c_hi) c_hi[q] = hi;
     }
     free(tmp);
   }

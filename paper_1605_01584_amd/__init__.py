@@ -418,6 +418,7 @@ def threshold_edges(z, zd: ZDesc, thr: float, cap: int, cfg: Optional[TileCfg] =
 
 def permtest(z, zd: ZDesc, perms, out=None, stream=None, validate: bool = True):
     """Counts of |r_perm| >= |r_obs| over the P rows of perms (device int32 P x l).
+    z in the "fp32" or "split" layout (the arithmetic follows the layout).
     validate=True checks on the device that every row is a permutation."""
     torch = _torch()
     if perms.dtype != torch.int32 or perms.dim() != 2 or perms.shape[1] != zd.l:

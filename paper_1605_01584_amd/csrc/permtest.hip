@@ -27,6 +27,8 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBlk = 32;       // profiles per side of a job
 constexpr int kWaves = 16;
@@ -59,7 +61,7 @@ size_t lds_bytes(int64_t l_pad) {
 // beyond l (padding: A and B are zero there) their own index, exactly as
 // the identity does.
 template <bool ALIGNED>
-__device__ __forceinline__ i32x4 perm_load(const int32_t *__restrict__ row, int64_t l, int k0) {
+__device__ __forceinline__ i32x4 perm_load(const int32_t *__restrict__ row, int l, int k0) {
   if constexpr (ALIGNED) {  // l % 4 == 0: a group is wholly inside or outside
     return *reinterpret_cast<const i32x4 *>(row + (k0 < l ? k0 : 0));
   } else {
@@ -208,6 +210,227 @@ __global__ __launch_bounds__(kThreads, 1) void permtest_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16x3 variant.  Z in the split layout (per 128-byte chunk the BF16
+// hi parts of 32 samples, then their lo parts); r = sum of lo.hi + hi.lo +
+// hi.hi products (v_mfma_f32_32x32x16_bf16), the arithmetic of the split
+// all-pairs tiles.
+//
+// LDS: A rows are the chunks as stored (pitch 4 l_pad + 16 bytes, an odd
+// number of 16-byte units); B rows hold one 32-bit word per sample, hi in
+// the low half and lo in the high half (pitch l_pad + 1 words), so a single
+// ds_read_b32 gather of sample pi(k) brings both BF16 operands of the
+// sample.  Lane (i, g) at step t takes samples k = 16t + 8g + e, e = 0..7:
+// its A hi and lo operands are one 16-byte unit each (unit 2(t mod 2) + g
+// of chunk t/2, and the unit four further on), its B operands come from 8
+// gathers regrouped into a hi and a lo vector.
+//
+// Samples k >= l (padding) are zero in A, so whatever finite B value their
+// index selects adds exactly zero: permutation indices are loaded with the
+// address clamped into the row and used as loaded.
+//
+// NP permutations per pass share every A read; WAVES waves split the
+// permutations, wave w taking p = w, w + WAVES, ...; slot 0 of a wave's first
+// pass is the identity (the observed r).
+
+__device__ __forceinline__ bool bf16_is_nan(uint32_t h) { return (h & 0x7fffu) > 0x7f80u; }
+
+// Indices of samples k0 .. k0 + 7 of one permutation row (byte offset off of
+// k0).  The row's buffer descriptor spans exactly its l entries: a load past
+// them returns 0, a valid index (see above).  Rows start on any 4-byte
+// boundary unless ALIGNED (l % 4 == 0 and a 16-byte aligned matrix).
+template <bool ALIGNED>
+__device__ __forceinline__ void idx_load(__amdgpu_buffer_rsrc_t rs, uint32_t off, i32x4 (&d)[2]) {
+  if constexpr (ALIGNED) {
+    d[0] = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    d[1] = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      d[e >> 2][e & 3] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * e, 0, 0);
+  }
+}
+
+// One step (16 samples) of NP accumulators: gathers, hi/lo regrouping
+// (v_perm_b32: the low halves of two words, then their high halves) and the
+// three products per accumulator.
+template <int NP, bool IDENT0>
+__device__ __forceinline__ void step_split(const unsigned char *__restrict__ arow,
+                                           const uint32_t *__restrict__ brow, int t, int g,
+                                           const i32x4 (&idx)[NP][2], f32x16 (&acc)[NP]) {
+  const int kb = 16 * t + 8 * g;
+  const unsigned char *ap = arow + (t >> 1) * 128 + ((2 * (t & 1) + g) << 4);
+  const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(ap));
+  const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(ap + 64));
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    uint32_t wd[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      wd[e] = (IDENT0 && j == 0) ? brow[kb + e] : brow[idx[j][e >> 2][e & 3]];
+    u32x4 h, o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      h[q] = __builtin_amdgcn_perm(wd[2 * q + 1], wd[2 * q], 0x05040100u);
+      o[q] = __builtin_amdgcn_perm(wd[2 * q + 1], wd[2 * q], 0x07060302u);
+    }
+    const bf16x8 bh = __builtin_bit_cast(bf16x8, h);
+    const bf16x8 bl = __builtin_bit_cast(bf16x8, o);
+    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[j], 0, 0, 0);
+    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[j], 0, 0, 0);
+    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[j], 0, 0, 0);
+  }
+}
+
+// One pass over all samples.  The indices of step t + 1 are loaded before
+// step t runs, into the other of two register sets (steps go in pairs: nt
+// is even), so a step never waits for a load it issued itself.
+template <bool ALIGNED, int NP, bool IDENT0>
+__device__ __forceinline__ void pass_split(const unsigned char *__restrict__ arow,
+                                           const uint32_t *__restrict__ brow,
+                                           const __amdgpu_buffer_rsrc_t (&rs)[NP], int nt, int g,
+                                           f32x16 (&acc)[NP]) {
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[j][v] = 0.0f;
+  i32x4 even[NP][2], odd[NP][2];
+  const uint32_t o0 = 32 * g;  // byte offset of sample 8g
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+    if (!(IDENT0 && j == 0)) idx_load<ALIGNED>(rs[j], o0, even[j]);
+  // (scheduling barriers keep each group of loads ahead of the step it
+  // overlaps: the compiler would otherwise sink them next to their use)
+  for (int t = 0; t < nt; t += 2) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (!(IDENT0 && j == 0)) idx_load<ALIGNED>(rs[j], o0 + 64 * (t + 1), odd[j]);
+    __builtin_amdgcn_sched_barrier(0);
+    step_split<NP, IDENT0>(arow, brow, t, g, even, acc);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (!(IDENT0 && j == 0)) idx_load<ALIGNED>(rs[j], o0 + 64 * (t + 2), even[j]);
+    __builtin_amdgcn_sched_barrier(0);
+    step_split<NP, IDENT0>(arow, brow, t + 1, g, odd, acc);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Descriptor over permutation row p (l entries).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t perm_row(const int32_t *perms, int64_t p, int l) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(perms + p * l), (short)0, 4 * l, 0x00020000);
+}
+
+template <bool ALIGNED, int NP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 1) void permtest_split_kernel(
+    const unsigned char *__restrict__ z, int64_t row_bytes, int64_t n, int64_t l, int64_t l_pad,
+    int64_t mb, const int32_t *__restrict__ perms, int32_t P, int32_t *__restrict__ counts) {
+  constexpr int kT = 64 * WAVES;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int64_t pa = 4 * pitch_a(l_pad);  // bytes
+  const int64_t pb = pitch_b(l_pad);      // words
+  unsigned char *sA = dyn;
+  uint32_t *sB = reinterpret_cast<uint32_t *>(dyn + kBlk * pa);
+  int32_t *sC = reinterpret_cast<int32_t *>(dyn + kBlk * pa + (kBlk * pb * 4 + 15) / 16 * 16);
+
+  const int tid = threadIdx.x;
+  // the wave index in an SGPR: permutation rows are then scalar base addresses
+  const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = lane & 31, g = lane >> 5;
+  const int nt = (int)(l_pad / 16);
+  const int64_t njobs = mb * (mb + 1) / 2;
+  const int64_t G = gridDim.x;
+  const int64_t u4 = l_pad / 4;   // 16-byte units per row
+  const int64_t g8 = l_pad / 8;   // groups of 8 samples per row
+
+  for (int64_t J = xcd_slot(blockIdx.x, G); J < njobs; J += G) {
+    const Cell cell = tri_cell(mb, J);
+    const int64_t y0 = cell.y * kBlk, x0 = cell.x * kBlk;
+    __syncthreads();  // the previous job is done with sA, sB, sC
+    for (int64_t q = tid; q < kBlk * u4; q += kT) {
+      const int64_t r = q / u4, u = q % u4;
+      *reinterpret_cast<u32x4 *>(sA + r * pa + 16 * u) =
+          *reinterpret_cast<const u32x4 *>(z + (y0 + r) * row_bytes + 16 * u);
+    }
+    for (int64_t q = tid; q < kBlk * g8; q += kT) {
+      // samples 32c + 8s .. + 7: hi in unit s of chunk c, lo in unit s + 4
+      const int64_t r = q / g8, c = (q % g8) >> 2, s = q & 3;
+      const unsigned char *src = z + (x0 + r) * row_bytes + c * 128 + 16 * s;
+      const u32x4 hv = *reinterpret_cast<const u32x4 *>(src);
+      const u32x4 lv = *reinterpret_cast<const u32x4 *>(src + 64);
+      uint32_t *d = sB + r * pb + 32 * c + 8 * s;
+#pragma unroll
+      for (int q2 = 0; q2 < 4; ++q2) {
+        d[2 * q2] = (hv[q2] & 0xffffu) | (lv[q2] << 16);
+        d[2 * q2 + 1] = (hv[q2] >> 16) | (lv[q2] & 0xffff0000u);
+      }
+    }
+    for (int q = tid; q < kBlk * kBlk; q += kT) sC[q] = 0;
+    __syncthreads();
+
+    if (w < P) {
+      const unsigned char *arow = sA + (int64_t)i * pa;
+      const uint32_t *brow = sB + (int64_t)i * pb;
+      // accumulator register v of lane (i, g): row 8(v/4) + 4g + v%4, column
+      // i; each pass adds its hits to the job's counts in LDS at once, so no
+      // count stays in registers
+      int32_t *crow = sC + (4 * g) * kBlk + i;
+      f32x16 acc[NP], robs;
+      {
+        // the observed r in slot 0, permutations w, w + WAVES, ... after it;
+        // a slot past P repeats permutation w and is not counted
+        __amdgpu_buffer_rsrc_t rs[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          const int64_t p = w + (int64_t)WAVES * (j - 1);
+          rs[j] = perm_row(perms, j > 0 && p < P ? p : w, (int)l);
+        }
+        pass_split<ALIGNED, NP, true>(arow, brow, rs, nt, g, acc);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) robs[v] = fabsf(clamp_unit(acc[0][v]));
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          int c = 0;
+#pragma unroll
+          for (int j = 1; j < NP; ++j)
+            if (w + (int64_t)WAVES * (j - 1) < P) c += (fabsf(clamp_unit(acc[j][v])) >= robs[v]) ? 1 : 0;
+          atomicAdd(crow + (8 * (v >> 2) + (v & 3)) * kBlk, c);
+        }
+      }
+      for (int64_t m0 = NP - 1; w + WAVES * m0 < P; m0 += NP) {
+        __amdgpu_buffer_rsrc_t rs[NP];
+        const int64_t p0 = w + WAVES * m0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          const int64_t p = p0 + (int64_t)WAVES * j;
+          rs[j] = perm_row(perms, p < P ? p : p0, (int)l);
+        }
+        pass_split<ALIGNED, NP, false>(arow, brow, rs, nt, g, acc);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          int c = 0;
+#pragma unroll
+          for (int j = 0; j < NP; ++j)
+            if (p0 + (int64_t)WAVES * j < P) c += (fabsf(clamp_unit(acc[j][v])) >= robs[v]) ? 1 : 0;
+          atomicAdd(crow + (8 * (v >> 2) + (v & 3)) * kBlk, c);
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < kBlk * kBlk; q += kT) {
+      const int r = q / kBlk, c = q % kBlk;
+      const int64_t y = y0 + r, x = x0 + c;
+      if (y < x && x < n) {
+        // degenerate profiles are NaN rows of Z; sample 0's hi part shows it
+        const bool nan = bf16_is_nan(*reinterpret_cast<const uint16_t *>(sA + r * pa)) ||
+                         bf16_is_nan(sB[c * pb] & 0xffffu);
+        counts[packed_index(n, y, x)] = nan ? -1 : sC[q];
+      }
+    }
+  }
+}
+
 // LDS one workgroup may allocate: the device's figure when a device is
 // present, else gfx950's 160 KiB.
 int64_t max_lds_per_block() {
@@ -223,13 +446,18 @@ int64_t max_lds_per_block() {
 }  // namespace
 
 int64_t permtest_max_l(int mode) {
-  if (mode != PCC_FP32) return 0;
-  // largest multiple of 32 whose LDS footprint fits one workgroup
+  if (mode != PCC_FP32 && mode != PCC_SPLIT_BF16X3) return 0;
+  // largest multiple of 32 whose LDS footprint fits one workgroup (both
+  // modes store 4 bytes per sample)
   const int64_t cap = max_lds_per_block();
   int64_t lp = 0;
   while (lds_bytes(lp + 32) <= (size_t)cap) lp += 32;
   return lp;
 }
+
+// Split kernel shape: permutations per pass and waves per workgroup.
+constexpr int kSplitNP = 2;
+constexpr int kSplitWaves = 16;
 
 hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *perms, int32_t P,
                            int32_t *counts, int cus, hipStream_t st) {
@@ -237,7 +465,17 @@ hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *pe
   const int64_t jobs = mb * (mb + 1) / 2;
   const size_t lds = lds_bytes(zd.l_pad);
   const bool aligned = (zd.l % 4) == 0 && ((reinterpret_cast<uintptr_t>(perms) & 15) == 0);
-  const void *k = aligned ? (const void *)permtest_kernel<true> : (const void *)permtest_kernel<false>;
+  const bool split = zd.mode == PCC_SPLIT_BF16X3;
+  const void *k;
+  int threads;
+  if (split) {
+    k = aligned ? (const void *)permtest_split_kernel<true, kSplitNP, kSplitWaves>
+                : (const void *)permtest_split_kernel<false, kSplitNP, kSplitWaves>;
+    threads = 64 * kSplitWaves;
+  } else {
+    k = aligned ? (const void *)permtest_kernel<true> : (const void *)permtest_kernel<false>;
+    threads = kThreads;
+  }
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int64_t grid = cus;
@@ -246,7 +484,7 @@ hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *pe
   int64_t rb = zd.row_bytes, n = zd.n, l = zd.l, lp = zd.l_pad;
   void *args[] = {(void *)&zp, (void *)&rb, (void *)&n, (void *)&l, (void *)&lp, (void *)&mb,
                   (void *)&perms, (void *)&P, (void *)&counts};
-  return hipLaunchKernel(k, dim3((unsigned)grid), dim3(kThreads), args, lds, st);
+  return hipLaunchKernel(k, dim3((unsigned)grid), dim3(threads), args, lds, st);
 }
 
 }  // namespace pcc

@@ -152,7 +152,10 @@ def test_permtest_limit_is_lds_bound():
     # one it uses the device's limit.  Either way a positive multiple of 32.
     lim = pcc.permtest_max_l("fp32")
     assert lim > 0 and lim % 32 == 0
-    assert pcc.permtest_max_l("bf16") == 0
+    # split stores 4 bytes per sample too: the same limit
+    assert pcc.permtest_max_l("split") == lim
+    assert pcc.permtest_max_l("bf16") == 0 and pcc.permtest_max_l("fp16") == 0
+    assert pcc.permtest_max_l("fp64") == 0
 
 
 def test_fp64_and_xy_argument_errors():

@@ -193,6 +193,33 @@ def test_permcounts_vs_numpy(oracle_mod):
         assert abs(gap[q] - np.min(np.abs(rp - robs))) <= 1e-12
 
 
+def test_permcounts_band_bounds(oracle_mod):
+    """c_lo / c_hi against numpy corrcoef; band 0 collapses both onto the
+    count, a band of 2 (wider than any |r| difference) opens them to 0 and P."""
+    rng = np.random.default_rng(19)
+    n, l, P = 9, 20, 40
+    X = rng.standard_normal((n, l))
+    perms = np.stack([rng.permutation(l) for _ in range(P)]).astype(np.int32)
+    I, J = np.triu_indices(n, 1)
+    c, _, lo, hi = oracle_mod.permcounts(X, perms, I, J, band=0.0)
+    assert np.array_equal(lo, c) and np.array_equal(hi, c)
+    c, _, lo, hi = oracle_mod.permcounts(X, perms, I, J, band=2.0)
+    assert np.all(lo == 0) and np.all(hi == P)
+    band = 0.03
+    c, _, lo, hi = oracle_mod.permcounts(X, perms, I, J, band=band)
+    for q, (i, j) in enumerate(zip(I, J)):
+        robs = abs(np.corrcoef(X[i], X[j])[0, 1])
+        rp = np.array([abs(np.corrcoef(X[i], X[j][perms[p]])[0, 1]) for p in range(P)])
+        d = rp - robs
+        # decisions within 1e-12 of an edge may go either way in rounding
+        if np.all(np.abs(np.abs(d) - band) > 1e-12):
+            assert lo[q] == int(np.sum(d >= band)) and hi[q] == int(np.sum(d >= -band))
+    assert np.all(lo <= c) and np.all(c <= hi) and np.any(lo < hi)
+    X[4] = 2.0
+    c, _, lo, hi = oracle_mod.permcounts(X, perms, [4, 0], [5, 4], band=band)
+    assert np.all(lo == -1) and np.all(hi == -1) and np.all(c == -1)
+
+
 def test_permcounts_nan_pair(oracle_mod):
     X = np.random.default_rng(1).standard_normal((3, 8))
     X[2] = 1.0
