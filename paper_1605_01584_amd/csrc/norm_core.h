@@ -45,7 +45,7 @@ template <typename TIn, int MODE> struct CacheOf {
 };
 
 template <typename TIn, int E, bool VEC>
-__device__ __forceinline__ void load_unit(const TIn *row, int64_t l, int64_t k0, TIn (&v)[E]) {
+__device__ __forceinline__ void load_unit(const TIn *row, int l, int k0, TIn (&v)[E]) {
   if (VEC && k0 + E <= l) {
     if constexpr (sizeof(TIn) == 4 && E == 2) {
       const float2 f = *reinterpret_cast<const float2 *>(row + k0);
@@ -116,50 +116,65 @@ __device__ __forceinline__ void store_unit(unsigned char *zr, int64_t u, const d
 }
 
 // Transform row `row` (< n) of x into row zr of Z.  Called by the G lanes
-// of a group (G = 64: a whole wave).
+// of a group (G = 64: a whole wave).  Lane j owns units j, j + G, j + 2G, ...
+// of the padded row; the first kCache of them stay in registers (in the
+// input type) for all three passes, the rest are re-read.  Sample indices
+// are 32-bit (l <= 2^21).  A cached unit the row does not have (at or past
+// l_pad) reads as zeros: adding +0.0 leaves the FP64 sums unchanged, and the
+// third pass stores only the units the row has.
 // VEC: the row starts 16-byte aligned and a unit of E samples can be read
 // with 16-byte loads (the caller checks the pointer and the pitch).
 template <typename TIn, int MODE, int kCache, bool VEC>
-__device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_t l, int64_t l_pad,
-                                              unsigned char *__restrict__ zr, double *stats_row,
-                                              int32_t *n_degenerate, double out_scale,
-                                              int G = 64) {
+__device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_t l64,
+                                              int64_t l_pad, unsigned char *__restrict__ zr,
+                                              double *stats_row, int32_t *n_degenerate,
+                                              double out_scale, int G = 64) {
   constexpr int E = UnitOf<MODE>::E;
+  const int l = (int)l64;
+  const int units = (int)(l_pad / E);
   const int lane = threadIdx.x & (G - 1);
-  const int64_t units = l_pad / E;
+  // cached units the row has at all: the same for every lane of the wave
+  // (all its rows have length l), so the bound is a scalar branch
+  const int nc = (units + G - 1) / G;
   TIn cache[kCache][E];  // the row stays in registers in its input type
   // pass 1: sum
   double s = 0.0;
 #pragma unroll
   for (int c = 0; c < kCache; ++c) {
-    const int64_t u = lane + G * c;
-    if (u < units) {
-      load_unit<TIn, E, VEC>(xr, l, u * E, cache[c]);
+    if (c < nc) {
+      load_unit<TIn, E, VEC>(xr, l, (lane + G * c) * E, cache[c]);
 #pragma unroll
       for (int e = 0; e < E; ++e) s += (double)cache[c][e];
     }
   }
-  for (int64_t u = lane + (int64_t)G * kCache; u < units; u += G) {
+  for (int u = lane + G * kCache; u < units; u += G) {
     TIn v[E];
     load_unit<TIn, E, VEC>(xr, l, u * E, v);
 #pragma unroll
     for (int e = 0; e < E; ++e) s += (double)v[e];
   }
   const double mean = group_sum(s, G) / (double)l;
+  // The cache is re-converted in each pass rather than kept in FP64 (which
+  // would double its registers): the empty asm hides that the values did not
+  // change.
+#pragma unroll
+  for (int c = 0; c < kCache; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e) asm volatile("" : "+v"(cache[c][e]));
   // pass 2: sum of squared deviations (padding samples excluded)
   double q = 0.0;
 #pragma unroll
   for (int c = 0; c < kCache; ++c) {
-    const int64_t u = lane + G * c;
-    if (u < units) {
+    if (c < nc) {
+      const int k0 = (lane + G * c) * E;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const double d = (double)cache[c][e] - mean;
-        q += (u * E + e < l) ? d * d : 0.0;
+        q += (k0 + e < l) ? d * d : 0.0;
       }
     }
   }
-  for (int64_t u = lane + (int64_t)G * kCache; u < units; u += G) {
+  for (int u = lane + G * kCache; u < units; u += G) {
     TIn v[E];
     load_unit<TIn, E, VEC>(xr, l, u * E, v);
 #pragma unroll
@@ -178,19 +193,23 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
     if (degenerate && n_degenerate) atomicAdd(n_degenerate, 1);
   }
   const double inv = degenerate ? (double)NAN : out_scale / sqrt(m2);
+#pragma unroll
+  for (int c = 0; c < kCache; ++c)
+#pragma unroll
+    for (int e = 0; e < E; ++e) asm volatile("" : "+v"(cache[c][e]));
   // pass 3: transformed samples, zero padding
 #pragma unroll
   for (int c = 0; c < kCache; ++c) {
-    const int64_t u = lane + G * c;
-    if (u < units) {
+    if (c < nc) {
+      const int u = lane + G * c;
       double o[E];
 #pragma unroll
       for (int e = 0; e < E; ++e)
         o[e] = (u * E + e < l) ? ((double)cache[c][e] - mean) * inv : 0.0;
-      store_unit<MODE, E>(zr, u, o);
+      if (u < units) store_unit<MODE, E>(zr, u, o);
     }
   }
-  for (int64_t u = lane + (int64_t)G * kCache; u < units; u += G) {
+  for (int u = lane + G * kCache; u < units; u += G) {
     TIn v[E];
     double o[E];
     load_unit<TIn, E, VEC>(xr, l, u * E, v);

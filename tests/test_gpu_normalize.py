@@ -68,7 +68,7 @@ def test_config1_fp64_input(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("l", [2, 3, 63, 64, 65, 1000, 2049, 4097])
+@pytest.mark.parametrize("l", [2, 3, 63, 64, 65, 200, 1000, 2049, 4097])
 def test_ragged_lengths_fp32_input(mode, l):
     rng = np.random.default_rng(l)
     X = (rng.standard_normal((37, l)) * 3 + 5).astype(np.float32)
