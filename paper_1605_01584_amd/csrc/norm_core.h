@@ -30,6 +30,18 @@ __device__ __forceinline__ double group_sum(double v, int G) {
   return v;
 }
 
+// Lanes that own one row in the variable transformation: the fewest of 4,
+// 8, ..., 64 whose registers hold a padded row at 32 samples per lane, so
+// short rows share a wave (at least 4 lanes, so that a row's loads still
+// cover 64 contiguous bytes or more).  One rule for the single-matrix and the
+// batched kernels: the lane count fixes the order of the FP64 sums, and both
+// must produce the same Z.
+inline int norm_lanes(int64_t l_pad) {
+  int g = 4;
+  while (g < 64 && (int64_t)g * 32 < l_pad) g *= 2;
+  return g;
+}
+
 // Samples per 16-byte output unit.
 template <int MODE> struct UnitOf {
   static constexpr int E = (MODE == PCC_FP64) ? 2 : ((MODE == PCC_FP32) ? 4 : 8);
