@@ -129,12 +129,15 @@ template <int EPI> struct Epi {
     else
       return y < x && x < zv.n;
   }
-  // rv is already clamped (NaN kept: it fails |rv| >= thr).
+  // rv is already clamped (NaN kept: it fails |rv| >= thr).  r is stored
+  // with ordinary (L2 write-back) stores: nontemporal ones measured about 1%
+  // slower on the packed triangle and the uneven batch, whose short jobs
+  // wait for their stores at the next job's first copy.
   template <typename T>
   static __device__ __forceinline__ void emit(const EpiArgs &ea, int64_t rb, int64_t y, int64_t x,
                                               T rv) {
     if constexpr (EPI == EPI_PACKED_F64) {
-      __builtin_nontemporal_store((double)rv, ea.r64 + rb + x);
+      ea.r64[rb + x] = (double)rv;
     } else if constexpr (kEdges) {
       if ((rv < (T)0 ? -rv : rv) >= (T)ea.thr) {
         const unsigned long long s = atomicAdd(ea.count, 1ull);
@@ -145,7 +148,7 @@ template <int EPI> struct Epi {
         }
       }
     } else {
-      __builtin_nontemporal_store((float)rv, ea.r + rb + x);
+      ea.r[rb + x] = (float)rv;
     }
   }
 };
