@@ -16,9 +16,10 @@
 //
 // Every wave first computes the observed r itself, by the same code path as
 // a permutation with the identity index, so an identity permutation
-// reproduces it bit for bit.  FP32 MFMA (v_mfma_f32_32x32x2_f32): the test
-// decides integers from |r| differences far below 1e-5, so it uses the most
-// accurate tile arithmetic.
+// reproduces it bit for bit.  Two kernels, by Z's layout: FP32 MFMA
+// (v_mfma_f32_32x32x2_f32, r within about 1e-7: the test decides integers
+// from |r| differences) and split-BF16x3 (three v_mfma_f32_32x32x16_bf16 per
+// 16 samples, about 5x the FP32 rate, r within split's 1e-5).
 #include "pcc_internal.h"
 
 namespace pcc {
@@ -226,8 +227,9 @@ __global__ __launch_bounds__(kThreads, 1) void permtest_kernel(
 // gathers regrouped into a hi and a lo vector.
 //
 // Samples k >= l (padding) are zero in A, so whatever finite B value their
-// index selects adds exactly zero: permutation indices are loaded with the
-// address clamped into the row and used as loaded.
+// index selects adds exactly zero: the permutation indices are loaded through
+// a buffer descriptor that spans the row's l entries, and a load past them
+// returns index 0.
 //
 // NP permutations per pass share every A read; WAVES waves split the
 // permutations, wave w taking p = w, w + WAVES, ...; slot 0 of a wave's first
