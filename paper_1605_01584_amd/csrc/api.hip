@@ -269,7 +269,7 @@ pcc_status pcc_allpairs_to_host(const pcc_zdesc *zd, const void *z, float *r_hos
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // K0 K1 C0 C1
   for (int k = 0; k < 4; ++k)
     if (note_hip(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming)) != hipSuccess) {
-      for (int q = 0; q < k; ++q) hipEventDestroy(ev[q]);
+      for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
       return PCC_E_HIP;
     }
   hipEvent_t *K = ev, *C = ev + 2;
@@ -313,9 +313,10 @@ pcc_status pcc_allpairs_to_host(const pcc_zdesc *zd, const void *z, float *r_hos
       on_pass(prev_first, prev_count, user);
     }
   }
-  hipStreamSynchronize(xs);
-  hipStreamSynchronize(cs);
-  for (int k = 0; k < 4; ++k) hipEventDestroy(ev[k]);
+  // drain both streams before the events go, also after an error
+  if (note_hip(hipStreamSynchronize(xs)) != hipSuccess && rs == PCC_OK) rs = PCC_E_HIP;
+  if (note_hip(hipStreamSynchronize(cs)) != hipSuccess && rs == PCC_OK) rs = PCC_E_HIP;
+  for (int k = 0; k < 4; ++k) (void)hipEventDestroy(ev[k]);
   return rs;
 }
 
@@ -491,7 +492,7 @@ pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_
   hipEvent_t e0, e1;
   if (note_hip(hipEventCreate(&e0)) != hipSuccess) return PCC_E_HIP;
   if (note_hip(hipEventCreate(&e1)) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return PCC_E_HIP;
   }
   float best_t = INFINITY;
@@ -514,7 +515,10 @@ pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_
         break;
       }
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (note_hip(hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+        rs = PCC_E_HIP;
+        break;
+      }
       if (rep > 0) ts.push_back(ms);
     }
     if (rs != PCC_OK) break;
@@ -526,8 +530,8 @@ pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_
       best_i = (int)k;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rs != PCC_OK) return rs;
   if (best_i < 0) return PCC_E_ARG;
   *best = list[best_i];

@@ -341,24 +341,27 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
         break;
       case PCC_BF16: e = launch_batch<PCC_BF16>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
       case PCC_FP16: e = launch_batch<PCC_FP16>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
+      default: break;  // refused above
     }
     hipGraph_t g = nullptr;
-    note_hip(e);
+    (void)note_hip(e);
     const hipError_t e2 = note_hip(hipStreamEndCapture(cs, &g));
     if (e != hipSuccess || e2 != hipSuccess || !g) {
       rs = PCC_E_HIP;
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
     } else {
       p->graph = g;
       if (note_hip(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         p->graph = nullptr;
         rs = PCC_E_HIP;
       }
     }
   }
-  hipStreamDestroy(cs);
+  if (note_hip(hipStreamDestroy(cs)) != hipSuccess && rs == PCC_OK) rs = PCC_E_HIP;
   if (rs != PCC_OK) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     free(p);
     return rs;
   }
