@@ -45,7 +45,6 @@ struct BatchDesc {
 
 constexpr size_t kCounterBytes = 256;
 constexpr int kCounterStride = 16;  // the two job counters, 128 bytes apart
-constexpr int kBatchCacheSamples = 32;  // input samples cached per lane
 
 // Workspace: [job counters | descriptor table | job0 of every dataset |
 // first row group of every dataset], each part 256-byte aligned.  A
@@ -92,14 +91,16 @@ __global__ void batch_zero_kernel(unsigned long long *counters) {
 }
 
 // Row normalisation of a batch.  One kernel serves every input variant of
-// the batch (FP32/FP64, vector or scalar loads), so it caches 32 samples per
-// lane in every mode to keep the four inlined variants within two waves per
-// SIMD.  A row is owned by `lanes` lanes: short rows share a wave (16 or 32
-// lanes each), so a wave has several rows' loads in flight at once.
+// the batch (FP32/FP64, vector or scalar loads), with the single-matrix
+// kernel's row code and register cache.  A row is owned by `lanes` lanes:
+// short rows share a wave (4 to 32 lanes each), so a wave has several rows'
+// loads in flight at once.  Rows longer than the registers hold (more than
+// 2048 samples) read their remainder from memory again in the later passes
+// (the single-matrix kernel stages it in LDS instead).
 template <typename TIn, int MODE, bool VEC>
 __device__ __forceinline__ void batch_row(const TIn *xr, int64_t l, int64_t l_pad,
                                           unsigned char *zr, double out_scale, int lanes) {
-  normalize_row<TIn, MODE, kBatchCacheSamples / UnitOf<MODE>::E, VEC>(
+  normalize_row<TIn, MODE, CacheOf<TIn, MODE>::C, VEC>(
       xr, l, l_pad, zr, nullptr, nullptr, out_scale, lanes);
 }
 

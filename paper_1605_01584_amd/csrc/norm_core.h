@@ -47,13 +47,12 @@ template <int MODE> struct UnitOf {
   static constexpr int E = (MODE == PCC_FP64) ? 2 : ((MODE == PCC_FP32) ? 4 : 8);
 };
 
-// Input units cached in registers per lane: 32 samples (rows up to 2048
-// samples are read from HBM exactly once), 64 for FP32 output from FP32
-// input (rows up to 4096; that variant has the registers to spare).  Longer
-// rows re-read the rest in the later passes.
+// Input units cached in registers per lane: 32 samples, so a row of up to
+// 2048 samples held by a whole wave stays in registers for all three passes
+// (more would cost occupancy: 64 samples halve the waves per SIMD and
+// measured slower); the rest of a longer row is staged in LDS.
 template <typename TIn, int MODE> struct CacheOf {
-  static constexpr int C =
-      ((MODE == PCC_FP32 && sizeof(TIn) == 4) ? 64 : 32) / UnitOf<MODE>::E;
+  static constexpr int C = 32 / UnitOf<MODE>::E;
 };
 
 template <typename TIn, int E, bool VEC>
@@ -127,10 +126,27 @@ __device__ __forceinline__ void store_unit(unsigned char *zr, int64_t u, const d
   }
 }
 
+// Unit u of a row, from the group's LDS staging area when it holds it (slot
+// < spill_units), else from memory.
+template <typename TIn, int E, bool VEC>
+__device__ __forceinline__ void reload_unit(const TIn *row, int l, int u, int slot,
+                                            const TIn *spill, int spill_units, TIn (&v)[E]) {
+  if (slot < spill_units) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = spill[slot * E + e];
+  } else {
+    load_unit<TIn, E, VEC>(row, l, u * E, v);
+  }
+}
+
 // Transform row `row` (< n) of x into row zr of Z.  Called by the G lanes
 // of a group (G = 64: a whole wave).  Lane j owns units j, j + G, j + 2G, ...
 // of the padded row; the first kCache of them stay in registers (in the
-// input type) for all three passes, the rest are re-read.  Sample indices
+// input type) for all three passes.  The rest (rows longer than the
+// registers hold) are staged in the group's own LDS region `spill` during
+// the first pass, up to spill_units units, and read back from there by the
+// later passes; units beyond that are read from memory again.  Each lane
+// reads back only the units it wrote, so no barrier is needed.  Sample indices
 // are 32-bit (l <= 2^21).  A cached unit the row does not have (at or past
 // l_pad) reads as zeros: adding +0.0 leaves the FP64 sums unchanged, and the
 // third pass stores only the units the row has.
@@ -140,7 +156,9 @@ template <typename TIn, int MODE, int kCache, bool VEC>
 __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_t l64,
                                               int64_t l_pad, unsigned char *__restrict__ zr,
                                               double *stats_row, int32_t *n_degenerate,
-                                              double out_scale, int G = 64) {
+                                              double out_scale, int G = 64,
+                                              TIn *__restrict__ spill = nullptr,
+                                              int spill_units = 0) {
   constexpr int E = UnitOf<MODE>::E;
   const int l = (int)l64;
   const int units = (int)(l_pad / E);
@@ -162,6 +180,11 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
   for (int u = lane + G * kCache; u < units; u += G) {
     TIn v[E];
     load_unit<TIn, E, VEC>(xr, l, u * E, v);
+    const int slot = u - G * kCache;
+    if (slot < spill_units) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) spill[slot * E + e] = v[e];
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) s += (double)v[e];
   }
@@ -188,7 +211,7 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
   }
   for (int u = lane + G * kCache; u < units; u += G) {
     TIn v[E];
-    load_unit<TIn, E, VEC>(xr, l, u * E, v);
+    reload_unit<TIn, E, VEC>(xr, l, u, u - G * kCache, spill, spill_units, v);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const double d = (double)v[e] - mean;
@@ -224,7 +247,7 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
   for (int u = lane + G * kCache; u < units; u += G) {
     TIn v[E];
     double o[E];
-    load_unit<TIn, E, VEC>(xr, l, u * E, v);
+    reload_unit<TIn, E, VEC>(xr, l, u, u - G * kCache, spill, spill_units, v);
 #pragma unroll
     for (int e = 0; e < E; ++e) o[e] = (u * E + e < l) ? ((double)v[e] - mean) * inv : 0.0;
     store_unit<MODE, E>(zr, u, o);
