@@ -49,7 +49,7 @@ def _check(got, X, perms, I, J, mode):
 
 @pytest.mark.parametrize("mode", ["fp32", "split"])
 @pytest.mark.parametrize("n,l,P", [(300, 50, 40), (33, 7, 25), (600, 129, 12), (200, 96, 33),
-                                   (150, 64, 5), (97, 512, 17)])
+                                   (150, 64, 5), (97, 512, 17), (2, 10, 7), (40, 64, 1)])
 def test_small_all_pairs(mode, n, l, P):
     rng = np.random.default_rng(n + l + P)
     X, _ = workloads.planted(n, l, n, n_planted=5, dtype=np.float32)
