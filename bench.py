@@ -163,7 +163,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline step only")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (normalize, fp32, edges, fp64, xy, to_host, "
-                         "calibration, permtest, batched, big_edges), default all")
+                         "calibration, permtest, batched, big_edges, table1), default all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -412,8 +412,49 @@ def main():
         extras.update(bench_batched(pcc, workloads, stream, dev))
     if want("big_edges"):
         extras.update(bench_big_edges(pcc, workloads, stream, dev))
+    if want("table1"):
+        extras.update(bench_table1(pcc, workloads, stream, dev))
     out["extras"] = extras
     print(json.dumps(out), flush=True)
+
+
+# The paper's Table I: LightPCC in FP64 on one Xeon Phi 5110P, seconds for
+# n = 16,000 / 32,000 / 64,000 profiles of 5,000 uniform samples.  Context,
+# not a target: other hardware, and the paper's timing boundary is its own.
+TABLE1_PAPER_S = {16000: 27.4, 32000: 83.2, 64000: 285.4}
+
+
+def bench_table1(pcc, workloads, stream, dev):
+    """The paper's Table I workloads at the paper's precision: FP64 input,
+    FP64 transformation and tiles, FP64 packed r, data resident on the GPU."""
+    import torch
+    out = {}
+    for n in workloads.TABLE1_SIZES:
+        l = workloads.TABLE1_L
+        log(f"[bench] Table I workload n={n} l={l}, FP64")
+        x = torch.from_numpy(workloads.table1(n)).to(dev)
+        zd = pcc.z_layout(n, l, "fp64")
+        z = torch.empty(zd.bytes, dtype=torch.uint8, device=dev)
+        r = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device=dev)
+        cfg = pcc.default_cfg(zd)
+
+        def run():
+            pcc.normalize(x, "fp64", z=z)
+            pcc.allpairs_f64(z, zd, cfg, out=r)
+        run()
+        ms, _ = timed(run, 2, stream)
+        ps = n * (n - 1) // 2 * l
+        out[f"{n // 1000}K"] = {
+            "ms": ms, "pair_samples_per_s": ps / (ms * 1e-3),
+            "fp64_mfma_frac": 2.0 * ps / (ms * 1e-3) / PEAK["fp64"],
+            "paper_one_phi_s": TABLE1_PAPER_S[n],
+            "ratio_to_paper_one_phi": TABLE1_PAPER_S[n] / (ms * 1e-3)}
+        del x, z, r
+        torch.cuda.empty_cache()
+    return {"table1_fp64": {"workload": "the paper's Table I: n profiles x 5,000 U[0,1] samples, FP64 "
+                                        "transformation + FP64 tiles + FP64 packed r (end to end, data on "
+                                        "the GPU); paper_one_phi_s is the paper's single Xeon Phi 5110P "
+                                        "time, context only", **out}}
 
 
 def bench_permtest(pcc, workloads, stream, dev):

@@ -119,3 +119,21 @@ def test_config3_shape_sampled():
     err = np.abs(got - ref)
     print(f"config3 fp64 sampled: {len(I)} pairs, max|dr| = {err.max():.3e}")
     assert err.max() <= fp64_tol(4096)
+
+
+def test_paper_table1_16k_sampled():
+    """The paper's smallest Table I workload (16,000 profiles of 5,000
+    uniform samples) in FP64 end to end, 2048 seeded pairs and the triangle's
+    first and last pairs against the oracle."""
+    import paper_1605_01584_amd as pcc
+    X = workloads.table1(16000)
+    n, l = X.shape
+    z, zd = pcc.normalize(to_device(X), "fp64")
+    r = pcc.allpairs_f64(z, zd).cpu().numpy()
+    I, J = workloads.random_pairs(n, 2048, seed=1600)
+    I = np.concatenate([I, [0, n - 2]])
+    J = np.concatenate([J, [1, n - 1]])
+    ref = oracle.pearson_pairs(X, I, J)
+    err = np.abs(r[packed_pos(n, I, J)] - ref)
+    print(f"Table I 16K fp64: max|dr| = {err.max():.3e} (bound {fp64_tol(l):.1e})")
+    assert err.max() <= fp64_tol(l)

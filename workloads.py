@@ -20,6 +20,8 @@ them, see the evaluation section of the paper):
   ``module_size`` genes share a factor ``f_m ~ N(0,1)``:
   ``w_g = lam_g*f_m + sqrt(1-lam_g^2)*eps_g`` with ``lam_g ~ U[0.6, 0.95]``;
   value ``log2(1 + exp(2 + 1.5*w))`` (log-normal counts, log2 scale).
+* ``uniform_matrix``: entries i.i.d. U[0, 1], the paper's artificial data
+  (its Table I runs n = 16,000, 32,000 and 64,000 profiles of l = 5,000).
 """
 from __future__ import annotations
 
@@ -180,3 +182,18 @@ def config5_batch(D: int = 64):
 def config5_big(n: int = 65536, l: int = 2048) -> Tuple[np.ndarray, Planted]:
     """One n=65536 x l=2048 FP32 matrix in the config-1 distribution."""
     return planted(n, l, SEEDS[5] + 100, dtype=np.float32)
+
+
+# Table I of the paper: n profiles of 5,000 samples drawn uniformly from [0, 1].
+TABLE1_SIZES = (16000, 32000, 64000)
+TABLE1_L = 5000
+
+
+def uniform_matrix(n: int, l: int, seed: int) -> np.ndarray:
+    """n x l FP64 entries i.i.d. U[0, 1]."""
+    return np.random.default_rng(seed).random((n, l))
+
+
+def table1(n: int) -> np.ndarray:
+    """The paper's Table I workload with n profiles (FP64, seeded by n)."""
+    return uniform_matrix(n, TABLE1_L, 6000 + n // 1000)
