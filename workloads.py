@@ -21,7 +21,9 @@ them, see the evaluation section of the paper):
   ``w_g = lam_g*f_m + sqrt(1-lam_g^2)*eps_g`` with ``lam_g ~ U[0.6, 0.95]``;
   value ``log2(1 + exp(2 + 1.5*w))`` (log-normal counts, log2 scale).
 * ``uniform_matrix``: entries i.i.d. U[0, 1], the paper's artificial data
-  (its Table I runs n = 16,000, 32,000 and 64,000 profiles of l = 5,000).
+  (its Table I runs n = 16,000, 32,000 and 64,000 profiles of l = 5,000);
+  ``table3_shape``: an expression-shaped stand-in with the shape of the
+  paper's real compendium (17,555 x 5,072), whose values are not available.
 """
 from __future__ import annotations
 
@@ -197,3 +199,13 @@ def uniform_matrix(n: int, l: int, seed: int) -> np.ndarray:
 def table1(n: int) -> np.ndarray:
     """The paper's Table I workload with n profiles (FP64, seeded by n)."""
     return uniform_matrix(n, TABLE1_L, 6000 + n // 1000)
+
+
+# Table III of the paper runs a 17,555 x 5,072 microarray compendium, which is
+# not available; an expression-shaped matrix of that shape stands in for it.
+TABLE3_SHAPE = (17555, 5072)
+
+
+def table3_shape() -> np.ndarray:
+    """Expression-shaped FP64 matrix with the shape of the paper's real data."""
+    return expression(TABLE3_SHAPE[0], TABLE3_SHAPE[1], 7000, dtype=np.float64)[0]
