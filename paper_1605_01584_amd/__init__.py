@@ -3,7 +3,8 @@
 Argument marshalling only.  Every step of the computation runs in the HIP
 kernels of ``libpcc.so`` (see ``include/pcc.h`` for the C ABI); PyTorch is
 used for device memory and streams.  Importing this package fails loudly if
-the library has not been built (``python -m paper_1605_01584_amd.build``).
+the library has not been built (``python paper_1605_01584_amd/build.py`` or
+``python __graft_entry__.py build`` from the repository root).
 
 Names follow the C ABI: ``z_layout``, ``normalize``, ``allpairs``,
 ``allpairs_f64``, ``allpairs_to_host``, ``threshold_edges``, ``allpairs_xy``,
@@ -24,7 +25,8 @@ LIB_PATH = os.path.join(_HERE, "libpcc.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first "
-        "(python -m paper_1605_01584_amd.build). There is no CPU fallback.")
+        "(python paper_1605_01584_amd/build.py, or python __graft_entry__.py build from the "
+        "repository root). There is no CPU fallback.")
 
 # One HIP runtime per process: torch's HIP libraries load the runtime bundled
 # with torch under the name "libamdhip64.so" (through their own RPATH), while
