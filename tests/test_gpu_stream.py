@@ -1,8 +1,8 @@
 """Multi-pass all pairs into host memory (double-buffered passes of whole
-tile rows, each copied to its place in a pinned host triangle): the host
-triangle equals the single-launch device result bit for bit, passes arrive
-in order and have landed when reported, and the full-size run matches the
-oracle on sampled pairs."""
+tile rows, each copied to its place in a host triangle, pinned or pageable):
+the host triangle equals the single-launch device result bit for bit, passes
+arrive in order and have landed when reported, and the full-size run matches
+the oracle on sampled pairs."""
 import numpy as np
 import pytest
 
@@ -40,6 +40,26 @@ def test_matches_device_allpairs(mode, tile, order, band, rpp):
     ref = _device_ref(z, zd, cfg)
     host = pcc.allpairs_to_host(z, zd, rpp, cfg).numpy()
     assert np.array_equal(host, ref)
+
+
+@pytest.mark.parametrize("mode", ["split", "fp32"])
+@pytest.mark.parametrize("tile,order,band,rpp", [(128, 1, 4, 8), (256, 0, 1, 3)])
+def test_pageable_host_memory(mode, tile, order, band, rpp):
+    """Pageable host memory (the copies cannot run asynchronously to it): the
+    same triangle, every pass reported."""
+    import torch
+    import paper_1605_01584_amd as pcc
+    rng = np.random.default_rng(rpp)
+    X = rng.standard_normal((2100, 90)).astype(np.float32)
+    z, zd = pcc.normalize(to_device(X), mode)
+    cfg = pcc.TileCfg(tile, order, band, 0)
+    ref = _device_ref(z, zd, cfg)
+    out = torch.full((zd.n * (zd.n - 1) // 2,), float("nan"), dtype=torch.float32)
+    assert not out.is_pinned()
+    seen = []
+    pcc.allpairs_to_host(z, zd, rpp, cfg, out=out, on_pass=lambda f, c: seen.append((f, c)))
+    assert np.array_equal(out.numpy(), ref)
+    assert sum(c for _, c in seen) == len(ref)
 
 
 def test_passes_in_order_and_landed():
