@@ -249,9 +249,9 @@ pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
  *          its counts are meaningless.  The Python binding checks them.
  *   counts device int32, n(n-1)/2.
  * Supported modes: FP32 (FP32 MFMA; every r within about 1e-7 of exact) and
- * split-BF16x3 (three BF16 products per sample, about 5x the FP32 rate; r
- * within split's 1e-5, so a count can differ from the exact one only in
- * permutations whose |r| lies that close to |r_obs|).  The plain 16-bit
+ * split-BF16x3 (three BF16 products per sample, about 2.7x the FP32 kernel's
+ * rate; r within split's 1e-5, so a count can differ from the exact one only
+ * in permutations whose |r| lies that close to |r_obs|).  The plain 16-bit
  * modes are refused: their r error (1e-4 and more) would decide too many
  * counts.  l_pad <= pcc_permtest_max_l(mode). */
 pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
