@@ -406,7 +406,9 @@ __device__ __forceinline__ void do_tile_f64(const ZView &zv, const EpiArgs &ea, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[p][q][v] = 0.0;
 
-  u32x4 ca[2][FR], cb[2][FC], na[2][FR], nb[2][FC];
+  // Two fragment sets alternate between stages (the loop body runs twice
+  // per iteration with the sets' roles swapped), so no fragment is copied.
+  u32x4 a0[2][FR], b0[2][FC], a1[2][FR], b1[2][FC];
   __syncthreads();  // every wave is done reading the previous tile's stages
   dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8, 0u, smem, w);
   if (nch > 1) {
@@ -416,42 +418,26 @@ __device__ __forceinline__ void do_tile_f64(const ZView &zv, const EpiArgs &ea, 
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   __syncthreads();
+  auto read_stage = [&](const u32x4 *buf, u32x4(&fa)[2][FR], u32x4(&fb)[2][FC]) {
 #pragma unroll
-  for (int p = 0; p < FR; ++p) {
-    ca[0][p] = smem[aoff + p * 128 + u0];
-    ca[1][p] = smem[aoff + p * 128 + u1];
-  }
-#pragma unroll
-  for (int q = 0; q < FC; ++q) {
-    cb[0][q] = smem[boff + q * 128 + u0];
-    cb[1][q] = smem[boff + q * 128 + u1];
-  }
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) {
-      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
-      __syncthreads();  // stage c + 1 landed everywhere; stage c's buffer is free
-      const u32x4 *nxt = smem + ((c + 1) & 1) * 2 * OPU;
-#pragma unroll
-      for (int p = 0; p < FR; ++p) {
-        na[0][p] = nxt[aoff + p * 128 + u0];
-        na[1][p] = nxt[aoff + p * 128 + u1];
-      }
-#pragma unroll
-      for (int q = 0; q < FC; ++q) {
-        nb[0][q] = nxt[boff + q * 128 + u0];
-        nb[1][q] = nxt[boff + q * 128 + u1];
-      }
-      if (c + 2 < nch)
-        dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8,
-                        (uint32_t)(c + 2) * 128u, smem + (c & 1) * 2 * OPU, w);
+    for (int p = 0; p < FR; ++p) {
+      fa[0][p] = buf[aoff + p * 128 + u0];
+      fa[1][p] = buf[aoff + p * 128 + u1];
     }
+#pragma unroll
+    for (int q = 0; q < FC; ++q) {
+      fb[0][q] = buf[boff + q * 128 + u0];
+      fb[1][q] = buf[boff + q * 128 + u1];
+    }
+  };
+  auto mfma_stage = [&](const u32x4(&fa)[2][FR], const u32x4(&fb)[2][FC]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       f64x2 a[FR], b[FC];
 #pragma unroll
-      for (int p = 0; p < FR; ++p) a[p] = __builtin_bit_cast(f64x2, ca[h][p]);
+      for (int p = 0; p < FR; ++p) a[p] = __builtin_bit_cast(f64x2, fa[h][p]);
 #pragma unroll
-      for (int q = 0; q < FC; ++q) b[q] = __builtin_bit_cast(f64x2, cb[h][q]);
+      for (int q = 0; q < FC; ++q) b[q] = __builtin_bit_cast(f64x2, fb[h][q]);
 #pragma unroll
       for (int e = 0; e < 2; ++e)
 #pragma unroll
@@ -460,15 +446,32 @@ __device__ __forceinline__ void do_tile_f64(const ZView &zv, const EpiArgs &ea, 
           for (int q = 0; q < FC; ++q)
             acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p][e], b[q][e], acc[p][q], 0, 0, 0);
     }
-    if (c + 1 < nch) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int p = 0; p < FR; ++p) ca[h][p] = na[h][p];
-#pragma unroll
-        for (int q = 0; q < FC; ++q) cb[h][q] = nb[h][q];
-      }
-    }
+  };
+  // Stage c with a stage after it: after the barrier read stage c + 1 into
+  // the other set and copy stage c + 2 (if any) into the buffer stage c used,
+  // then stage c's MFMAs.  Every stage in the loop reads its successor (the
+  // last one is peeled off), so the waits for those reads stay exact.
+  auto stage = [&](int c, const u32x4(&fa)[2][FR], const u32x4(&fb)[2][FC], u32x4(&ga)[2][FR],
+                   u32x4(&gb)[2][FC]) {
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __syncthreads();  // stage c + 1 landed everywhere; stage c's buffer is free
+    read_stage(smem + ((c + 1) & 1) * 2 * OPU, ga, gb);
+    if (c + 2 < nch)
+      dma_stage<TILE>(rsa, rsb, lane_row_off, uoff_even, uoff_odd, row8,
+                      (uint32_t)(c + 2) * 128u, smem + (c & 1) * 2 * OPU, w);
+    mfma_stage(fa, fb);
+  };
+  read_stage(smem, a0, b0);
+  int c = 0;
+  for (; c + 2 < nch; c += 2) {
+    stage(c, a0, b0, a1, b1);
+    stage(c + 1, a1, b1, a0, b0);
+  }
+  if (c + 1 < nch) {  // two stages left
+    stage(c, a0, b0, a1, b1);
+    mfma_stage(a1, b1);
+  } else {            // one stage left
+    mfma_stage(a0, b0);
   }
 
   // Epilogue.  Lane (j, g4) holds column 16q + j of block (p, q); its
