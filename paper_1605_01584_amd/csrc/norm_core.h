@@ -167,26 +167,39 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
   // (all its rows have length l), so the bound is a scalar branch
   const int nc = (units + G - 1) / G;
   TIn cache[kCache][E];  // the row stays in registers in its input type
-  // pass 1: sum
+  // pass 1: sum.  All loads of a group of units are issued before any of
+  // them is used, so their latencies overlap (summed afterwards in the same
+  // order).
   double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < kCache; ++c)
+    if (c < nc) load_unit<TIn, E, VEC>(xr, l, (lane + G * c) * E, cache[c]);
 #pragma unroll
   for (int c = 0; c < kCache; ++c) {
     if (c < nc) {
-      load_unit<TIn, E, VEC>(xr, l, (lane + G * c) * E, cache[c]);
 #pragma unroll
       for (int e = 0; e < E; ++e) s += (double)cache[c][e];
     }
   }
-  for (int u = lane + G * kCache; u < units; u += G) {
-    TIn v[E];
-    load_unit<TIn, E, VEC>(xr, l, u * E, v);
-    const int slot = u - G * kCache;
-    if (slot < spill_units) {
+  constexpr int kTailGroup = 2;  // tail units loaded together
+  for (int u0 = lane + G * kCache; u0 < units; u0 += kTailGroup * G) {
+    TIn v[kTailGroup][E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) spill[slot * E + e] = v[e];
+    for (int j = 0; j < kTailGroup; ++j)
+      if (u0 + j * G < units) load_unit<TIn, E, VEC>(xr, l, (u0 + j * G) * E, v[j]);
+#pragma unroll
+    for (int j = 0; j < kTailGroup; ++j) {
+      const int u = u0 + j * G;
+      if (u < units) {
+        const int slot = u - G * kCache;
+        if (slot < spill_units) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) spill[slot * E + e] = v[j][e];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) s += (double)v[j][e];
+      }
     }
-#pragma unroll
-    for (int e = 0; e < E; ++e) s += (double)v[e];
   }
   const double mean = group_sum(s, G) / (double)l;
   // The cache is re-converted in each pass rather than kept in FP64 (which
