@@ -250,7 +250,8 @@ def main():
                 "kernel": f"tile_kernel<{mode},{cfg.tile}>",
                 "per_launch": f"{alg_flops:.4e} MFMA flops = 2 x {MFMA_PER_MAC[mode]} x "
                               f"n(n-1)/2 x l",
-                "useful_frac": (2.0 * pair_samples / (tile_avg * 1e-3)) / PEAK[dt]}
+                "useful_frac": (2.0 * pair_samples / (tile_avg * 1e-3)) / PEAK[dt],
+                "kernel_ms": tile_avg}
 
     out = {
         "metric": "PCC pair-samples/s + MFMA util; split-BF16 vs FP32 path at max|dr|<=1e-5",
