@@ -84,7 +84,7 @@ def cpu_baseline(X, seconds=10.0):
     import oracle
     import workloads
     n, l = X.shape
-    blocks = workloads.check_blocks(n, nblocks=256, seed=3)
+    blocks = workloads.check_blocks(n, nblocks=2048, seed=3)
     done_pairs, t0, used = 0, time.perf_counter(), 0
     results = []
     while used < len(blocks) and time.perf_counter() - t0 < seconds:

@@ -453,6 +453,11 @@ __device__ __forceinline__ void do_tile_f64(const ZView &zv, const EpiArgs &ea, 
   // last one is peeled off), so the waits for those reads stay exact.
   auto stage = [&](int c, const u32x4(&fa)[2][FR], const u32x4(&fb)[2][FC], u32x4(&ga)[2][FR],
                    u32x4(&gb)[2][FC]) {
+    // The MFMAs touch registers only, so the scheduler would sink the
+    // previous stage's MFMAs below this wait, which then finds the copy of
+    // stage c + 1 still in flight with nothing left to cover it: keep them
+    // above it.
+    __builtin_amdgcn_sched_barrier(0);
     asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
     __syncthreads();  // stage c + 1 landed everywhere; stage c's buffer is free
     read_stage(smem + ((c + 1) & 1) * 2 * OPU, ga, gb);
