@@ -38,7 +38,7 @@ struct BatchDesc {
   int32_t xt;
   int32_t tile;
   int32_t nchunks;
-  int32_t lanes;  // lanes per row in the transformation (16, 32 or 64)
+  int32_t lanes;  // lanes per row in the transformation (4, 8, 16, 32 or 64)
   float scale;
   double out_scale;  // normalisation multiplier (FP16 layout: sqrt(l))
 };

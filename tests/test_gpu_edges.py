@@ -1,11 +1,14 @@
 """pcc_threshold_edges on the GPU: the edge set against the oracle (pairs
 within 1e-5 of the threshold excluded from the exact-set check), against the
-same library's packed output, capacity overflow, and full-size runs."""
+same library's packed output, capacity overflow, and full-size runs, whose
+edge lists are compared whole with the oracle's full scans stored under
+tests/golden/."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+from golden_scan import read_scan
 from gpu_util import packed_pos, to_device
 
 pytestmark = pytest.mark.gpu
@@ -90,6 +93,58 @@ def test_threshold_zero_and_degenerate():
     assert 7 not in set(ij.ravel().tolist())
     ij, rv, cnt = _edges(z, zd, 1.5, 16)
     assert cnt == 0
+
+
+def _check_against_scan(ij, rv, cnt, thr, band, scan):
+    """The edge set equals the full scan's outside the band around the
+    threshold; every reported r is within 1e-5 of the oracle's."""
+    got = _set(ij)
+    assert cnt == len(got)
+    near = {p for p, r in scan.items() if abs(abs(r) - thr) <= band}
+    want = {p for p, r in scan.items() if abs(r) >= thr}
+    assert (got - near) == (want - near)
+    for (i, j), r in zip(map(tuple, ij.tolist()), rv.tolist()):
+        if (i, j) in scan:
+            assert abs(r - scan[(i, j)]) <= 1e-5, (i, j)
+    return got, want
+
+
+@pytest.mark.parametrize("mode", ["split", "fp32"])
+def test_config3_edges_equal_full_scan(mode):
+    """n = 32768, l = 4096, |r| >= 0.8: the whole edge list against the
+    oracle's scan of all 536,854,528 pairs."""
+    import paper_1605_01584_amd as pcc
+    thr, band, scan = read_scan("edges_n32768_l4096_thr0.8")
+    X, pl = workloads.config3()
+    z, zd = pcc.normalize(to_device(X), mode)
+    ij, rv, cnt = _edges(z, zd, thr, 1 << 16)
+    got, want = _check_against_scan(ij, rv, cnt, thr, band, scan)
+    planted = set(zip(np.minimum(pl.u, pl.v).tolist(), np.maximum(pl.u, pl.v).tolist()))
+    assert planted <= want
+
+
+def test_config5_big_edges_equal_full_scan():
+    """n = 65536, l = 2048, split, |r| >= 0.9 (the large run of the
+    uneven-batch workload, as the benchmark times it): the whole edge list
+    against the oracle's scan of all 2,147,450,880 pairs, and r on 16 check
+    blocks of the packed output."""
+    import torch
+    import paper_1605_01584_amd as pcc
+    thr, band, scan = read_scan("edges_n65536_l2048_thr0.9")
+    X, pl = workloads.config5_big()
+    n = X.shape[0]
+    z, zd = pcc.normalize(to_device(X), "split")
+    ij, rv, cnt = _edges(z, zd, thr, 1 << 16)
+    got, want = _check_against_scan(ij, rv, cnt, thr, band, scan)
+    planted = set(zip(np.minimum(pl.u, pl.v).tolist(), np.maximum(pl.u, pl.v).tolist()))
+    assert planted <= want
+    r = pcc.allpairs(z, zd)
+    blocks = workloads.check_blocks(n, nblocks=16, seed=65)
+    I, J = workloads.block_pairs(n, blocks)
+    ref = oracle.pearson_pairs(X, I, J)
+    assert np.max(np.abs(r[torch.from_numpy(packed_pos(n, I, J)).to(r.device)].cpu().numpy() - ref)) <= 1e-5
+    del r
+    torch.cuda.empty_cache()
 
 
 def test_config3_edges_full_size():

@@ -299,3 +299,32 @@ def test_xy_with_itself_is_the_symmetric_matrix(oracle_mod):
     d = np.diag(r).copy()
     assert np.isnan(d[5]) and np.all(np.isnan(r[5])) and np.all(np.isnan(r[:, 5]))
     np.testing.assert_allclose(np.delete(d, 5), 1.0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name,n,l", [("edges_n32768_l4096_thr0.8", 32768, 4096),
+                                      ("edges_n65536_l2048_thr0.9", 65536, 2048)])
+def test_stored_full_scans(oracle_mod, name, n, l):
+    """The stored full scans (tests/golden/make_edge_scans.py, oracle only)
+    parse, list pairs i < j in scan order with |r| >= threshold - band, hold
+    every planted pair of their workload, and agree with the oracle
+    recomputed on the listed pairs."""
+    import os
+    import workloads
+    from golden_scan import GOLDEN, read_scan
+    if not os.path.exists(os.path.join(GOLDEN, name + ".txt")):
+        pytest.fail(f"{name}.txt missing: run tests/golden/make_edge_scans.py")
+    thr, band, scan = read_scan(name)
+    assert band == 1e-5 and thr in (0.8, 0.9)
+    keys = list(scan)
+    assert keys == sorted(keys)
+    assert all(0 <= i < j < n for i, j in keys)
+    assert all(abs(r) >= thr - band for r in scan.values())
+    X, pl = (workloads.config3() if n == 32768 else workloads.config5_big())
+    assert X.shape == (n, l)
+    planted = set(zip(np.minimum(pl.u, pl.v).tolist(), np.maximum(pl.u, pl.v).tolist()))
+    strong = {p for p, r in scan.items() if abs(r) >= thr}
+    assert planted <= strong
+    I = np.array([i for i, _ in keys], dtype=np.int64)
+    J = np.array([j for _, j in keys], dtype=np.int64)
+    np.testing.assert_allclose(oracle_mod.pearson_pairs(X, I, J), [scan[k] for k in keys],
+                               rtol=0, atol=1e-15)
