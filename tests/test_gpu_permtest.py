@@ -110,12 +110,12 @@ def test_zero_permutations_and_degenerate_rows(mode):
 
 @pytest.mark.parametrize("mode", ["fp32", "split"])
 def test_config4_full_size_sampled(mode):
-    """n = 8192, l = 512, P = 1000 in one launch; 2048 seeded pairs plus the
-    planted pairs against the oracle."""
+    """n = 8192, l = 512, P = 1000 in one launch; 65,536 seeded pairs plus
+    the planted pairs against the oracle (each pair's 1000 permutations)."""
     X, pl, perms = workloads.config4()
     got = _gpu_counts(X, perms, mode)
     n = X.shape[0]
-    I, J = workloads.random_pairs(n, 2048, seed=404)
+    I, J = workloads.random_pairs(n, 65536, seed=404)
     I = np.concatenate([I, np.minimum(pl.u, pl.v)])
     J = np.concatenate([J, np.maximum(pl.u, pl.v)])
     g = got[packed_pos(n, I, J)]
