@@ -64,7 +64,9 @@ def test_graph_replays_agree():
 
 
 def test_config5_batch_sampled():
-    """64 datasets, n ~ U[500, 8000], l ~ U[50, 2000], split, one graph."""
+    """64 datasets, n ~ U[500, 8000], l ~ U[50, 2000], split, one graph:
+    per dataset 4 seeded 128 x 128 check blocks, 300 random pairs and the
+    planted pairs against the oracle."""
     import torch
     import paper_1605_01584_amd as pcc
     batch = workloads.config5_batch()
@@ -75,9 +77,10 @@ def test_config5_batch_sampled():
     total = 0
     for d, (X, pl) in enumerate(batch):
         n = X.shape[0]
+        BI, BJ = workloads.block_pairs(n, workloads.check_blocks(n, nblocks=4, seed=500 + d))
         I, J = workloads.random_pairs(n, 300, seed=d)
-        I = np.concatenate([I, np.minimum(pl.u, pl.v)])
-        J = np.concatenate([J, np.maximum(pl.u, pl.v)])
+        I = np.concatenate([BI, I, np.minimum(pl.u, pl.v)])
+        J = np.concatenate([BJ, J, np.maximum(pl.u, pl.v)])
         got = plan.r[d][torch.from_numpy(packed_pos(n, I, J)).cuda()].cpu().numpy()
         ref = oracle.pearson_pairs(X, I, J)
         assert np.max(np.abs(got - ref)) <= 1e-5, d
