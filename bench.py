@@ -94,12 +94,35 @@ def cpu_baseline(X, seconds=10.0):
         done_pairs += len(I)
         used += min(8, len(blocks) - used)
     dt = time.perf_counter() - t0
+    threads = oracle.num_threads()
+    # the same oracle on one core, over the first two blocks
+    I1, J1 = workloads.block_pairs(n, blocks[:2])
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.pearson_pairs(X, I1, J1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
     return {
-        "value": done_pairs * l / dt, "unit": "pair-samples/s", "cores": oracle.num_threads(),
+        "value": done_pairs * l / dt, "unit": "pair-samples/s", "cores": threads,
         "kind": "oracle",
         "sample": f"{used} seeded 128x128 check blocks ({done_pairs} pairs i<j) of the "
                   f"n={n} l={l} matrix, FP64 literal Eq. (1), {dt:.1f} s",
+        "single_core_value": len(I1) * l / dt1,
+        "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()},
     }, results
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def calibration(dev, stream):
