@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline step only")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (normalize, fp32, edges, fp64, xy, to_host, "
-                         "calibration, permtest, batched, big_edges, table1), default all")
+                         "calibration, permtest, batched, big_edges, table1, config1), default all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -425,6 +425,25 @@ def main():
         del z64, r64
         torch.cuda.empty_cache()
         extras["max_abs_dr_vs_fp64_oracle"] = {"pairs": int(len(I)), **acc}
+        # config 1 in full: the oracle over every pair, and every pair of the
+        # GPU paths against it
+        import oracle
+        X1, _ = workloads.config1()
+        n1, l1 = X1.shape
+        t1 = time.perf_counter()
+        ref1 = oracle.pearson_packed(X1)
+        dt1 = time.perf_counter() - t1
+        out["cpu_baseline"]["config1_full"] = {
+            "workload": f"n={n1} l={l1}, every pair", "s": dt1,
+            "pair_samples_per_s": (n1 * (n1 - 1) // 2) * l1 / dt1}
+        x1 = torch.from_numpy(X1).to(dev)
+        acc1 = {}
+        for m in ("fp64", "fp32", "split"):
+            z1, zd1 = pcc.normalize(x1, m)
+            r1 = pcc.allpairs_f64(z1, zd1) if m == "fp64" else pcc.allpairs(z1, zd1)
+            acc1[m] = float(np.max(np.abs(r1.cpu().numpy().astype(np.float64) - ref1)))
+        extras["config1_max_abs_dr_every_pair"] = {"pairs": int(len(ref1)), **acc1}
+        del x1
     else:
         out["cpu_baseline"] = None
 
@@ -438,6 +457,8 @@ def main():
         extras.update(bench_big_edges(pcc, workloads, stream, dev))
     if want("table1"):
         extras.update(bench_table1(pcc, workloads, stream, dev))
+    if want("config1"):
+        extras.update(bench_config1(pcc, workloads, stream, dev))
     out["extras"] = extras
     print(json.dumps(out), flush=True)
 
@@ -517,6 +538,32 @@ def bench_permtest(pcc, workloads, stream, dev):
         "equal_frac": float((d == 0).float().mean()), "max_abs_diff": int(d.max()),
         "speedup": out["permtest"]["ms"] / out["permtest_split"]["ms"]}
     return out
+
+
+def bench_config1(pcc, workloads, stream, dev):
+    """Config 1 (n = 2000, l = 256, FP64 input, every pair) end to end on the
+    GPU: transformation plus all pairs, in FP64, FP32 and split."""
+    import torch
+    log("[bench] config 1 end to end")
+    X, _ = workloads.config1()
+    n, l = X.shape
+    x = torch.from_numpy(X).to(dev)
+    ps = (n * (n - 1) // 2) * l
+    out = {"workload": f"n={n} l={l} FP64 input, transformation + every pair"}
+    for mode in ("fp64", "fp32", "split"):
+        zd = pcc.z_layout(n, l, mode)
+        z = torch.empty(zd.bytes, dtype=torch.uint8, device=dev)
+        if mode == "fp64":
+            r = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device=dev)
+            step = lambda: (pcc.normalize(x, mode, z=z), pcc.allpairs_f64(z, zd, out=r))
+        else:
+            r = torch.empty(n * (n - 1) // 2, dtype=torch.float32, device=dev)
+            step = lambda: (pcc.normalize(x, mode, z=z), pcc.allpairs(z, zd, out=r))
+        step()
+        ms, _ = timed(step, 20, stream)
+        out[mode] = {"ms": ms, "pair_samples_per_s": ps / (ms * 1e-3)}
+        del z, r
+    return {"config1": out}
 
 
 def bench_batched(pcc, workloads, stream, dev):
