@@ -161,6 +161,12 @@ __device__ __forceinline__ int64_t xcd_slot(int64_t b, int64_t G) {
 
 __device__ __forceinline__ int lds_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
 
+// Swizzle of the FP64 tile's LDS rows, whose fragment reads take 16 rows by
+// four 16-byte units per instruction.  Measured: the swizzle above, which
+// also flips the unit of rows 8-15, costs these reads four bank-conflict
+// cycles each; the row index mod 8 alone (or (r / 2) mod 8) none.
+__device__ __forceinline__ int lds_swz64(int r) { return r & 7; }
+
 // LDS unit of fragment s of half h for lane half g.
 template <int MODE> __device__ __forceinline__ int frag_unit(int h, int s, int g) {
   if constexpr (MODE == PCC_SPLIT_BF16X3)
@@ -388,13 +394,13 @@ __device__ __forceinline__ void do_tile_f64(const ZView &zv, const EpiArgs &ea, 
       __builtin_amdgcn_make_buffer_rsrc((void *)zb, (short)0, kPanelRange, 0x00020000);
   const int ro = lane >> 3;
   const uint32_t lane_row_off = (uint32_t)((8 * IPW * w + ro) * rb);
-  const uint32_t uoff_even = (uint32_t)(((lane & 7) ^ lds_swz(ro)) * 16);
-  const uint32_t uoff_odd = (uint32_t)(((lane & 7) ^ lds_swz(ro + 8)) * 16);
+  const uint32_t uoff_even = (uint32_t)(((lane & 7) ^ lds_swz64(ro)) * 16);
+  const uint32_t uoff_odd = (uint32_t)(((lane & 7) ^ lds_swz64(ro + 8)) * 16);
   const uint32_t row8 = (uint32_t)(8 * rb);
   const int nch = zv.nchunks;
   // rows 16p + j of a wave's band sit at row offsets that are multiples of
-  // 16 plus j, so their swizzle is lds_swz(j)
-  const int sw = lds_swz(j);
+  // 16 plus j, so their swizzle is lds_swz64(j)
+  const int sw = lds_swz64(j);
   const int aoff = (wr * WTR + j) * 8, boff = OPU + (wc * WTC + j) * 8;
   const int u0 = g4 ^ sw, u1 = (g4 + 4) ^ sw;
 
