@@ -57,7 +57,12 @@ template <typename TIn, int MODE> struct CacheOf {
 
 template <typename TIn, int E, bool VEC>
 __device__ __forceinline__ void load_unit(const TIn *row, int l, int k0, TIn (&v)[E]) {
-  if (VEC && k0 + E <= l) {
+  if (!VEC && k0 + E <= l) {
+    // a whole unit of a row that need not start 16-byte aligned: copied at
+    // the element type's alignment, which gfx950 loads with 16-byte (or
+    // 8-byte) vector loads just the same
+    __builtin_memcpy(v, row + k0, E * sizeof(TIn));
+  } else if (VEC && k0 + E <= l) {
     if constexpr (sizeof(TIn) == 4 && E == 2) {
       const float2 f = *reinterpret_cast<const float2 *>(row + k0);
       v[0] = f.x; v[1] = f.y;
@@ -150,8 +155,9 @@ __device__ __forceinline__ void reload_unit(const TIn *row, int l, int u, int sl
 // are 32-bit (l <= 2^21).  A cached unit the row does not have (at or past
 // l_pad) reads as zeros: adding +0.0 leaves the FP64 sums unchanged, and the
 // third pass stores only the units the row has.
-// VEC: the row starts 16-byte aligned and a unit of E samples can be read
-// with 16-byte loads (the caller checks the pointer and the pitch).
+// VEC: the row starts 16-byte aligned, so a unit of E samples is read with
+// aligned 16-byte loads (the caller checks the pointer and the pitch);
+// otherwise whole units are read at the element type's alignment.
 template <typename TIn, int MODE, int kCache, bool VEC>
 __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_t l64,
                                               int64_t l_pad, unsigned char *__restrict__ zr,
