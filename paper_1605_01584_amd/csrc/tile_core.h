@@ -370,10 +370,10 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
 }
 
 // FP64 tile (yt, xt), 128 x 128, same workgroup shape, LDS stages and DMA as
-// do_tile; each wave owns 32 x 64 = 2 x 4 blocks of 16 x 16 FP64
-// accumulators (v_mfma_f64_16x16x4_f64).  One FP64 MFMA is long, so whole
-// stages are pipelined: stage c + 1's fragments are read (after the stage
-// barrier) before stage c's 32 MFMAs are issued.
+// do_tile, with its own row swizzle (lds_swz64); each wave owns 32 x 64 =
+// 2 x 4 blocks of 16 x 16 FP64 accumulators (v_mfma_f64_16x16x4_f64).  One
+// FP64 MFMA is long, so whole stages are pipelined: stage c + 1's fragments
+// are read (after the stage barrier) before stage c's 32 MFMAs are issued.
 template <int EPI>
 __device__ __forceinline__ void do_tile_f64(const ZView &zv, const EpiArgs &ea, int64_t yt,
                                             int64_t xt, u32x4 *__restrict__ smem) {
