@@ -127,8 +127,9 @@ def test_edges_xy():
 
 def test_full_size_sampled():
     """16384 x 16384 cross pairs of l = 4096 (the benchmark's non-symmetric
-    leg: the two halves of the n = 32768 matrix), split tiles, sampled
-    against the oracle."""
+    leg: the two halves of the n = 32768 matrix), split tiles: every cell
+    written and identical under four schedules, sampled against the
+    oracle."""
     import torch
     import paper_1605_01584_amd as pcc
     Xall, _ = workloads.config3()
@@ -136,7 +137,15 @@ def test_full_size_sampled():
     X, Y = Xall[:h], Xall[h:]
     zx, zdx = pcc.normalize(to_device(X), "split")
     zy, zdy = pcc.normalize(to_device(Y), "split")
-    r = pcc.allpairs_xy(zx, zdx, zy, zdy)
+    # every cell is written (the output starts as NaN), the same by every schedule
+    r = torch.full((h, h), float("nan"), dtype=torch.float32, device="cuda")
+    pcc.allpairs_xy(zx, zdx, zy, zdy, out=r)
+    assert not bool(r.isnan().any())
+    for cfg in (pcc.TileCfg(256, 0, 1, 0), pcc.TileCfg(128, 1, 8, 0), pcc.TileCfg(256, 1, 8, 7)):
+        r2 = torch.full_like(r, float("nan"))
+        pcc.allpairs_xy(zx, zdx, zy, zdy, cfg, out=r2)
+        assert torch.equal(r2, r), cfg
+        del r2
     torch.cuda.synchronize()
     I, J = workloads.random_pairs(2 * h, 20000, seed=5)
     I, J = I % h, J % h
