@@ -72,11 +72,15 @@ def test_config5_batch_sampled():
     batch = workloads.config5_batch()
     xs = [to_device(X) for X, _ in batch]
     plan = pcc.BatchPlan(xs, "split")
+    for r in plan.r:
+        r.fill_(float("nan"))
     plan.launch()
     torch.cuda.synchronize()
     total = 0
     for d, (X, pl) in enumerate(batch):
         n = X.shape[0]
+        # every element of each triangle was written (they start as NaN)
+        assert bool(torch.isfinite(plan.r[d]).all()), d
         BI, BJ = workloads.block_pairs(n, workloads.check_blocks(n, nblocks=4, seed=500 + d))
         I, J = workloads.random_pairs(n, 300, seed=d)
         I = np.concatenate([BI, I, np.minimum(pl.u, pl.v)])

@@ -104,14 +104,17 @@ def test_edges_fp64():
 
 def test_config3_shape_sampled():
     """n = 32768, l = 4096 in FP64 (the benchmark's FP64 leg): the 128-wide
-    tile grid at full size, sampled blocks against the oracle."""
+    tile grid at full size writes every element of the triangle (the output
+    starts as NaN); sampled blocks against the oracle."""
     import torch
     import paper_1605_01584_amd as pcc
     X, _ = workloads.config3()
-    z, zd = pcc.normalize(to_device(X), "fp64")
-    r = pcc.allpairs_f64(z, zd)
-    torch.cuda.synchronize()
     n = X.shape[0]
+    z, zd = pcc.normalize(to_device(X), "fp64")
+    r = torch.full((n * (n - 1) // 2,), float("nan"), dtype=torch.float64, device="cuda")
+    pcc.allpairs_f64(z, zd, out=r)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(r).all())
     blocks = workloads.check_blocks(n, nblocks=8, seed=77)
     I, J = workloads.block_pairs(n, blocks)
     ref = oracle.pearson_pairs(X, I, J)

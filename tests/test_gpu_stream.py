@@ -106,10 +106,14 @@ def test_full_size_sampled():
     """n = 32768, l = 4096, split, 8 tile rows per pass (16 passes): the
     benchmark's streaming leg, sampled against the oracle."""
     import paper_1605_01584_amd as pcc
+    import torch
     X, _ = workloads.config3()
     n = X.shape[0]
     z, zd = pcc.normalize(to_device(X), "split")
-    host = pcc.allpairs_to_host(z, zd, 8).numpy()
+    out = torch.full((n * (n - 1) // 2,), float("nan"), dtype=torch.float32, pin_memory=True)
+    host = pcc.allpairs_to_host(z, zd, 8, out=out).numpy()
+    # every element of the host triangle was written (it starts as NaN)
+    assert np.isfinite(host).all()
     blocks = workloads.check_blocks(n, nblocks=16, seed=91)
     I, J = workloads.block_pairs(n, blocks)
     ref = oracle.pearson_pairs(X, I, J)
