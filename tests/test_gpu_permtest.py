@@ -25,12 +25,18 @@ def split_band(l):
 
 
 def _gpu_counts(X, perms, mode="fp32"):
+    """Counts of every pair; the output starts at -7, a value no count takes,
+    so a pair that kept it was never written."""
     import torch
     import paper_1605_01584_amd as pcc
     z, zd = pcc.normalize(to_device(X), mode)
-    c = pcc.permtest(z, zd, torch.from_numpy(perms).cuda())
+    n = X.shape[0]
+    c = torch.full((n * (n - 1) // 2,), -7, dtype=torch.int32, device="cuda")
+    pcc.permtest(z, zd, torch.from_numpy(perms).cuda(), out=c)
     torch.cuda.synchronize()
-    return c.cpu().numpy()
+    got = c.cpu().numpy()
+    assert not np.any(got == -7)
+    return got
 
 
 def _check(got, X, perms, I, J, mode):
