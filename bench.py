@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline step only")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (normalize, fp32, edges, fp64, xy, to_host, "
-                         "calibration, permtest, batched, big_edges, table1, config1), default all")
+                         "calibration, permtest, batched, big_edges, table1, config1, config2), default all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -459,6 +459,8 @@ def main():
         extras.update(bench_table1(pcc, workloads, stream, dev))
     if want("config1"):
         extras.update(bench_config1(pcc, workloads, stream, dev))
+    if want("config2"):
+        extras.update(bench_config2(pcc, workloads, stream, dev))
     out["extras"] = extras
     print(json.dumps(out), flush=True)
 
@@ -565,6 +567,38 @@ def bench_config1(pcc, workloads, stream, dev):
         out[mode] = {"ms": ms, "pair_samples_per_s": ps / (ms * 1e-3)}
         del z, r
     return {"config1": out}
+
+
+def bench_config2(pcc, workloads, stream, dev):
+    """Config 2 (n = 16384, l = 1024 expression-shaped FP32) on FP32 MFMA
+    tiles: the tile kernel alone and the step with the transformation."""
+    import torch
+    log("[bench] config 2, FP32 tiles")
+    X, _ = workloads.config2()
+    n, l = X.shape
+    x = torch.from_numpy(X).to(dev)
+    zd = pcc.z_layout(n, l, "fp32")
+    z = torch.empty(zd.bytes, dtype=torch.uint8, device=dev)
+    r = torch.empty(n * (n - 1) // 2, dtype=torch.float32, device=dev)
+    pcc.normalize(x, "fp32", z=z)
+    dflt = pcc.default_cfg(zd)
+    cfg, _ = pcc.autotune(z, zd, r, reps=3)    # the schedule for this shape, not timed
+    # each block warmed up, 30 runs of a 2 ms kernel per median
+    def block(fn):
+        for _ in range(3):
+            fn()
+        return timed(fn, 30, stream)[0]
+    default_ms = block(lambda: pcc.allpairs(z, zd, dflt, out=r))
+    tile_ms = block(lambda: pcc.allpairs(z, zd, cfg, out=r))
+    step_ms = block(lambda: (pcc.normalize(x, "fp32", z=z), pcc.allpairs(z, zd, cfg, out=r)))
+    ps = (n * (n - 1) // 2) * l
+    del x, z, r
+    torch.cuda.empty_cache()
+    return {"config2": {"workload": f"n={n} l={l} expression-shaped FP32, FP32 MFMA tiles, packed r",
+                        "tuned_cfg": [cfg.tile, cfg.order, cfg.band, cfg.grid],
+                        "tile_ms": tile_ms, "default_cfg_tile_ms": default_ms, "step_ms": step_ms,
+                        "pair_samples_per_s": ps / (step_ms * 1e-3),
+                        "mfma_frac": 2.0 * ps / (tile_ms * 1e-3) / PEAK["fp32"]}}
 
 
 def bench_batched(pcc, workloads, stream, dev):
