@@ -80,14 +80,19 @@ def test_ragged_lengths_fp32_input(mode, l):
     _check_values(Z, zd, U, mode, np.abs(X.astype(np.float64)).max(axis=1) / np.sqrt(m2))
 
 
-@pytest.mark.parametrize("ld", [101, 104, 128])
-def test_row_pitch(ld):
-    # ld = 101 is not a multiple of 4 floats: the scalar load path
-    rng = np.random.default_rng(ld)
-    X = rng.standard_normal((50, 100)).astype(np.float32)
-    U, _, _ = oracle.transform(X)
-    Z, zd, _, _ = _run(X, "fp32", ld=ld)
-    _check_values(Z, zd, U, "fp32")
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dtype,ld", [("float32", 101), ("float32", 103), ("float32", 104),
+                                      ("float32", 128), ("float64", 101), ("float64", 104)])
+def test_row_pitch(mode, dtype, ld):
+    """Rows that do not start 16-byte aligned (an odd pitch of floats or
+    doubles) take the unaligned unit loads; l = 100 and 99 leave whole units
+    and a partial last one."""
+    for l in (100, 99):
+        rng = np.random.default_rng(ld + l)
+        X = rng.standard_normal((50, l)).astype(dtype)
+        U, m, m2 = oracle.transform(X)
+        Z, zd, _, _ = _run(X, mode, ld=ld)
+        _check_values(Z, zd, U, mode, np.abs(X.astype(np.float64)).max(axis=1) / np.sqrt(m2))
 
 
 def test_unit_norm_and_zero_sum():
