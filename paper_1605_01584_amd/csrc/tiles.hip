@@ -25,17 +25,29 @@ struct UniformArgs {
   int64_t mc;     // tile columns (non-symmetric)
   int64_t j0;     // first tile id of this launch
   int64_t njobs;  // one past the last tile id: mr(mr+1)/2 or mr mc for a whole run
+  int64_t split;  // work units from j0 on: tile ids j0 + u for u < split, then
+  int64_t nunits; // quarters: unit split + 4 s + q is quarter q of tile j0 + split + s
   int32_t order;
   int32_t band;
 };
 
 template <int EPI> constexpr bool is_rect() { return EPI == EPI_RECT || EPI == EPI_RECT_EDGES; }
 
+// Persistent workgroups take work units u = slot, slot + G, ...  A unit is
+// a whole tile job, except that the symmetric 256-wide FP32 kernels may
+// compute the jobs of a last, mostly empty round as four 128 x 128 quarters
+// each (units from a.split on), so that every workgroup has a share of it.
+// Both tile widths sum every pair's samples in the same order: r is the
+// same.  The BF16 modes gain nothing from it: the chip is power-limited
+// there, and the compute units busy in a sparse last round run at a higher
+// clock.
 template <int MODE, int TILE, int EPI>
 __global__ __launch_bounds__(kTileThreads, 1) void tile_kernel(UniformArgs a) {
   __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
   const int64_t G = gridDim.x;
-  for (int64_t J = a.j0 + xcd_slot(blockIdx.x, G); J < a.njobs; J += G) {
+  int64_t u = xcd_slot(blockIdx.x, G);
+  for (; u < a.split; u += G) {
+    const int64_t J = a.j0 + u;
     Cell tc;
     if constexpr (is_rect<EPI>())
       tc = rect_cell(a.mr, a.mc, a.order, a.band, J);
@@ -45,6 +57,22 @@ __global__ __launch_bounds__(kTileThreads, 1) void tile_kernel(UniformArgs a) {
       do_tile_f64<EPI>(a.zv, a.ea, tc.y, tc.x, smem);
     else
       do_tile<MODE, TILE, EPI>(a.zv, a.ea, tc.y, tc.x, smem);
+  }
+  // A loop of its own, so that what the 128-wide code keeps in registers is
+  // not held through the whole-tile loop.
+  if constexpr (TILE == 256 && !is_rect<EPI>() && MODE == PCC_FP32) {
+    if (u < a.nunits) {
+      // copies of the last 256-wide call may still be in flight into LDS
+      // units that the 128-wide layout uses differently
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    for (; u < a.nunits; u += G) {
+      const int64_t s = u - a.split;
+      const Cell tc = tile_of_job(a.mr, a.order, a.band, a.j0 + a.split + (s >> 2));
+      const int64_t qy = 2 * tc.y + ((s >> 1) & 1), qx = 2 * tc.x + (s & 1);
+      if (qy > qx) continue;  // the lower quarter of a diagonal tile
+      do_tile<MODE, 128, EPI>(a.zv, a.ea, qy, qx, smem);
+    }
   }
 }
 
@@ -117,11 +145,28 @@ UniformArgs make_args_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &
   return a;
 }
 
+// Work units of a launch over tile ids [j0, njobs) on `grid` workgroups:
+// whole tiles, and for the symmetric 256-wide FP32 kernels the quarters of
+// the last round's tiles when that round would leave more than half of the
+// workgroups idle (its quarters then take at most two 128-wide rounds).
+void plan_units(int mode, int tile, int epi, int64_t grid, UniformArgs &a) {
+  const int64_t N = a.njobs - a.j0;
+  a.split = N;
+  a.nunits = N;
+  const bool quarters = tile == 256 && mode == PCC_FP32 && (epi == EPI_PACKED || epi == EPI_EDGES);
+  if (!quarters || N <= 0 || grid < 2) return;
+  const int64_t T = N - (N - 1) / grid * grid;  // tiles of the last round
+  if (2 * T > grid) return;
+  a.split = N - T;
+  a.nunits = a.split + 4 * T;
+}
+
 hipError_t launch(int mode, UniformArgs a, int tile, int epi, int grid, hipStream_t st) {
   const void *k = kernel_for(mode, tile, epi);
   if (!k) return hipErrorInvalidValue;
   if (grid < 1) grid = 1;
-  if (a.njobs - a.j0 < grid) grid = (int)(a.njobs - a.j0);
+  plan_units(mode, tile, epi, grid, a);
+  if (a.nunits < grid) grid = (int)a.nunits;
   if (grid < 1) return hipSuccess;  // empty range
   void *args[] = {(void *)&a};
   return hipLaunchKernel(k, dim3(grid), dim3(kTileThreads), args, 0, st);

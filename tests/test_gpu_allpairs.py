@@ -70,6 +70,40 @@ def test_schedules_give_identical_results(c1, mode):
     assert np.array_equal(outs[0][1], outs[3][1])
 
 
+def _quarter_plan(N, grid):
+    """Mirror of the launcher's rule: with 256-wide symmetric FP32 tiles, a
+    last round of T <= grid / 2 tiles runs as 128-wide quarters."""
+    T = N - (N - 1) // grid * grid
+    return (N - T, 4 * T) if 2 * T <= grid else (N, 0)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "split"])
+def test_last_round_quarters(c1, mode):
+    """256-wide schedules on grids whose last round holds no quarters, some
+    (one tile or several, diagonal tiles among them) or only quarters (one
+    round at most half full; FP32 computes those as 128-wide quarters, the
+    other modes as whole tiles): r is bit-identical to the 128-wide schedule
+    and matches the oracle, edges included."""
+    import paper_1605_01584_amd as pcc
+    X, _, ref = c1
+    m = (X.shape[0] + 255) // 256
+    N = m * (m + 1) // 2                       # 36 tiles
+    ref128 = _gpu_allpairs(X, mode, pcc.TileCfg(128, 1, 2, 0))
+    assert np.max(np.abs(ref128 - ref)) <= TOL[mode]
+    kinds = set()
+    z, zd = pcc.normalize(to_device(X), mode)
+    for order, band, grid in [(1, 4, N), (0, 1, 10), (1, 8, 7), (0, 1, 16), (1, 2, 2 * N), (0, 1, 5)]:
+        whole, quarters = _quarter_plan(N, grid)
+        kinds.add("none" if quarters == 0 else ("only" if whole == 0 else "some"))
+        cfg = pcc.TileCfg(256, order, band, grid)
+        r = _gpu_allpairs(X, mode, cfg)
+        assert np.array_equal(r, ref128), (order, band, grid)
+        ij, rv, cnt = pcc.threshold_edges(z, zd, 0.5, 1 << 12, cfg)
+        want = np.nonzero(np.abs(ref128) >= 0.5)[0]
+        assert cnt == len(want), (order, band, grid)
+    assert kinds == {"none", "some", "only"}
+
+
 @pytest.mark.parametrize("mode", ["fp32", "split"])
 def test_run_twice_bit_identical(c1, mode):
     X, _, _ = c1
