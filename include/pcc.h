@@ -101,7 +101,10 @@ typedef struct {
  *              tile rows; a band is walked column by column, so consecutive
  *              ids share row and column panels.  Both are bijections.
  *   grid:  persistent workgroups, 0 = one per compute unit times occupancy.
- * Identical results for every schedule (no split-K, no atomics on r). */
+ * Identical results for every schedule (no split-K, no atomics on r): with
+ * 256-wide FP32 tiles, a last round of the persistent grid that would leave
+ * more than half of the workgroups idle is computed as 128-wide quarters,
+ * which sum every pair's samples in the same order. */
 typedef struct {
   int32_t tile;
   int32_t order;
