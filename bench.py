@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--mode", default="split")
     ap.add_argument("--no-extras", action="store_true", help="headline step only")
     ap.add_argument("--legs", default="all",
-                    help="comma list of extra legs (normalize, fp32, edges, fp64, xy, to_host, "
+                    help="comma list of extra legs (normalize, fp32, modes16, edges, fp64, xy, to_host, "
                          "calibration, permtest, batched, big_edges, table1, config1, config2), default all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -309,6 +309,20 @@ def main():
             "mfma_frac": 2.0 * pair_samples / (t32 * 1e-3) / PEAK["fp32"],
             "split_speedup_over_fp32": t32 / tile_avg}
         del z32
+    if want("modes16"):
+        # the plain 16-bit formats on the same shape (one MFMA per product)
+        for m16 in ("bf16", "fp16"):
+            zd16 = pcc.z_layout(n, l, m16)
+            z16 = torch.empty(zd16.bytes, dtype=torch.uint8, device=dev)
+            pcc.normalize(x, m16, z=z16)
+            cfg16 = pcc.default_cfg(zd16)
+            for _ in range(2):
+                pcc.allpairs(z16, zd16, cfg16, out=r)
+            t16, _ = timed(lambda: pcc.allpairs(z16, zd16, cfg16, out=r), 5, stream)
+            extras[m16 + "_path"] = {
+                "tile_ms": t16, "pair_samples_per_s": pair_samples / (t16 * 1e-3),
+                "mfma_frac": 2.0 * pair_samples / (t16 * 1e-3) / PEAK[m16]}
+            del z16
     if want("edges"):
         # edges epilogue (|r| >= 0.8)
         cap = 1 << 20
