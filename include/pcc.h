@@ -62,6 +62,15 @@ typedef enum { PCC_IN_F32 = 0, PCC_IN_F64 = 1 } pcc_in_t;
  *   PCC_FP32          z in FP32, v_mfma_f32_32x32x2_f32.
  *   PCC_SPLIT_BF16X3  z = hi + lo with hi = bf16(z), lo = bf16(z - hi);
  *                     r = hi.hi + hi.lo + lo.hi, v_mfma_f32_32x32x16_bf16.
+ *                     Each product z_i[k] z_j[k] is then off by at most
+ *                     3 * 2^-16 |z_i[k] z_j[k]|, so |dr| <= 3 * 2^-16 (about
+ *                     4.6e-5) by Cauchy-Schwarz for any data.  On profiles of
+ *                     continuous values the errors have random signs and
+ *                     |dr| stays below 1e-5 once l > 64; rows of at most 64
+ *                     samples are therefore computed in FP32 (pcc_tile_arith).
+ *                     Profiles of a few repeated levels (binary data, say) make
+ *                     the errors systematic: |dr| can reach about 1.1e-5 at any
+ *                     l; use PCC_FP32 or PCC_FP64 for such data.
  *   PCC_BF16          z in BF16.
  *   PCC_FP16          z*sqrt(l) in FP16 (unit RMS entries), r = acc / l.
  *   PCC_FP64          z in FP64, FP64 accumulators, v_mfma_f64_16x16x4_f64:
@@ -83,7 +92,10 @@ typedef enum {
  *   SPLIT: 32 bf16 hi values followed by the 32 matching bf16 lo values;
  *   FP64:  16 doubles.
  * Samples l..l_pad-1 and rows n..n_pad-1 are zero.  n_pad is a multiple of
- * 256 and l_pad a multiple of kchunk. */
+ * 256 and l_pad a multiple of kchunk.
+ * Exception: a SPLIT layout with l_pad <= 64 (rows of one or two chunks)
+ * holds 32 FP32 values per chunk, exactly as the FP32 layout does, and its
+ * tiles compute in FP32 (see pcc_tile_arith). */
 typedef struct {
   int64_t n, l;          /* profiles and samples per profile */
   int64_t n_pad, l_pad;  /* padded sizes */
@@ -134,7 +146,15 @@ pcc_status pcc_z_layout(int64_t n, int64_t l, pcc_mode_t mode, pcc_zdesc *out);
 /* Default tile schedule for a layout (host only, pure). */
 pcc_status pcc_default_cfg(const pcc_zdesc *zd, pcc_tile_cfg *out);
 
-/* Variable transformation, Eq. (4) (a1 of the hot path).
+/* Arithmetic the tile kernels use for a layout (host only, pure): zd->mode,
+ * except PCC_FP32 for a PCC_SPLIT_BF16X3 layout with l_pad <= 64, whose rows
+ * pcc_normalize writes in FP32 (over so few samples the split's per-product
+ * errors do not average below 1e-5; Eq. (5) is then evaluated in FP32).
+ * -1 for an invalid layout. */
+int32_t pcc_tile_arith(const pcc_zdesc *zd);
+
+/* Variable transformation, Eq. (4) and the variable transformation
+ * algorithm (Sec. III-E).
  *   x      device, n rows of l samples, row pitch ldx elements (ldx >= l),
  *          element type xt.
  *   z      device, zd->bytes bytes, written in the layout of *zd, padding
@@ -149,12 +169,18 @@ pcc_status pcc_normalize(const void *x, pcc_in_t xt, int64_t ldx,
                          const pcc_zdesc *zd, void *z, double *stats,
                          int32_t *n_degenerate, void *stream);
 
-/* Bytes of device workspace an operation needs (0 = none; the workspace
- * pointer may then be NULL).  op: 0 allpairs, 1 edges, 2 permtest. */
+/* Bytes of device workspace an operation needs.  op: 0 allpairs, 1 edges,
+ * 2 permtest.  It is 0 for every op and layout: the tile kernels keep their
+ * staging in LDS and registers, the edge counter is the caller's `count`,
+ * and the permutation counts accumulate in LDS.  The `workspace` arguments
+ * of those calls are therefore unused and may be NULL; they remain so that
+ * a future kernel needing scratch does not change the ABI.  (The uneven
+ * batch sizes its workspace with pcc_batch_workspace_size, the multi-pass
+ * call its buffers with pcc_stream_buffer_bytes.) */
 size_t pcc_workspace_size(const pcc_zdesc *zd, int32_t op);
 
-/* All pairs (a2-a5 of the hot path): tile jobs placed by the bijection of
- * Eq. (16)-(19), each tile of Z Z^T contracted on MFMA, and
+/* All pairs (Sec. III-C, the tiled multithreaded kernel): tile jobs placed
+ * by the bijection of Eq. (16)-(19), each tile of Z Z^T contracted on MFMA, and
  *   r[J'] = clamp(Z_y . Z_x, -1, 1)   for every 0 <= y < x < n,
  * with J' = F_{n-1}(y) + (x - 1) - y the strict-upper-triangle index (the
  * diagonal-free adaptation of Eq. (9)-(10)): row y of the triangle is
@@ -202,8 +228,11 @@ pcc_status pcc_allpairs_to_host(const pcc_zdesc *zd, const void *z, float *r_hos
                                 pcc_pass_fn on_pass, void *user,
                                 void *compute_stream, void *copy_stream);
 
-/* Thresholded edge list (a4 (ii)): every pair y < x with |r| >= thr (r
- * clamped as above; NaN never qualifies) is appended as ij[2s] = y,
+/* Thresholded edge list: the co-expression network construction that
+ * motivates all-pairs correlation (Sec. I) keeps the pairs whose |r|
+ * reaches a threshold.  Every pair y < x with |r| >= thr (r = Z_y . Z_x by
+ * Eq. (5), clamped to the [-1, 1] that Eq. (1) bounds r to; NaN never
+ * qualifies) is appended as ij[2s] = y,
  * ij[2s+1] = x, rv[s] = r for a slot s < cap.  *count (device int64) is
  * zeroed by the call and receives the true number of such pairs, which may
  * exceed cap (then only cap are stored: call again with a larger list).
@@ -239,8 +268,10 @@ pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
                                   int32_t *ij, float *rv, int64_t cap, int64_t *count,
                                   const pcc_tile_cfg *cfg, void *workspace, void *stream);
 
-/* Permutation test (a6), one persistent launch for all P permutations.
- * For every pair y < x:
+/* Permutation test: the significance test by random permutations that the
+ * evaluation (Sec. IV-A) motivates, at least 1,000 iterations of all-pairs
+ * r on permuted data, in one persistent launch for all P permutations.
+ * For every pair y < x (r by Eq. (5)):
  *   r_obs = Z_y . Z_x,  r_p = sum_k Z_y[k] Z_x[perm_p[k]],
  *   counts[J'] = #{p : |r_p| >= |r_obs|}  (ties counted; -1 if r_obs is NaN)
  * The second operand (column x) is permuted; Z's mean and norm are
@@ -265,7 +296,7 @@ pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
  * 0 for modes it does not support. */
 int64_t pcc_permtest_max_l(pcc_mode_t mode);
 
-/* ---- Uneven batches (a7) ----------------------------------------------
+/* ---- Uneven batches -----------------------------------------------------
  * One item per dataset.  The plan uploads a descriptor table into the
  * caller's workspace and records, into one hipGraph, the batched
  * normalisation (all datasets) and one persistent all-pairs kernel whose
@@ -295,13 +326,19 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items,
                                  pcc_mode_t mode, void *workspace,
                                  size_t workspace_bytes, void *stream,
                                  pcc_batch_plan **plan);
-/* Replay the plan's graph on `stream` (asynchronous). */
+/* Replay the plan's graph on `stream` (asynchronous).  The plan's job
+ * counters live in its workspace and every launch resets and consumes them:
+ * a plan may have at most one launch in flight.  Launches of one plan on one
+ * stream are ordered and safe; launching it again on another stream first
+ * requires that stream to wait for the previous launch (an event), otherwise
+ * the two launches race on the counters and tiles are skipped or computed
+ * twice.  Distinct plans (distinct workspaces) may run concurrently. */
 pcc_status pcc_batch_plan_launch(pcc_batch_plan *plan, void *stream);
 /* Total tile jobs of the plan (for accounting). */
 int64_t pcc_batch_plan_jobs(const pcc_batch_plan *plan);
 pcc_status pcc_batch_plan_destroy(pcc_batch_plan *plan);
 
-/* ---- Job maps (a2), host side, for tests and tooling -------------------
+/* ---- Job maps, host side, for tests and tooling -------------------------
  * Inclusive map over an m x m triangle (diagonal counted in), Eq. (9)-(15):
  * J = F_m(y) + x - y with F_m(y) = y(2m - y + 1)/2; inverse by Eq. (14)-(15)
  * evaluated in FP64, then corrected in int64 so that F_m(y) <= J < F_m(y+1)
@@ -331,12 +368,19 @@ pcc_status pcc_cells_device(int64_t m, int32_t diag, int64_t J0, int64_t count,
 /* ---- Autotuning ---------------------------------------------------------
  * Time each candidate schedule of pcc_allpairs on the caller's z (r is
  * overwritten) with hipEvents and return the fastest in *best.  `cands`
- * may be NULL (built-in candidate list); times_ms (host, nullable) gets
- * the median time of every candidate. */
+ * may be NULL with ncands == 0: the built-in list of
+ * pcc_autotune_default_count() candidates (both tile sizes, the paper's row
+ * order and bands of 2, 4, 8 and 16 tile rows).  times_ms (host, nullable)
+ * gets the median time of every candidate timed: ncands entries, or
+ * pcc_autotune_default_count() entries for the built-in list, so it must
+ * hold max(ncands, pcc_autotune_default_count()) floats to be safe. */
 pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r,
                         const pcc_tile_cfg *cands, int32_t ncands,
                         int32_t reps, pcc_tile_cfg *best, float *times_ms,
                         void *stream);
+
+/* Number of candidates in pcc_autotune's built-in list. */
+int32_t pcc_autotune_default_count(void);
 
 /* Number of compute units of the current device (0 if none). */
 int32_t pcc_device_cus(void);

@@ -123,6 +123,8 @@ _sig("pcc_rect_tile_order_host", _i32, _i64, _i64, _cfgp, _i64, _i64, _vp, _vp)
 _sig("pcc_cells_device", _i32, _i64, _i32, _i64, _i64, _vp, _vp, _vp)
 _sig("pcc_autotune", _i32, _zdp, _vp, _vp, _cfgp, _i32, _i32, _cfgp, _vp, _vp)
 _sig("pcc_device_cus", _i32)
+_sig("pcc_autotune_default_count", _i32)
+_sig("pcc_tile_arith", _i32, _zdp)
 
 EXPORTED = [
     "pcc_status_string", "pcc_version", "pcc_last_hip_error", "pcc_last_hip_error_string",
@@ -134,6 +136,7 @@ EXPORTED = [
     "pcc_batch_plan_launch", "pcc_batch_plan_jobs", "pcc_batch_plan_destroy", "pcc_job_of_cell",
     "pcc_cell_of_job", "pcc_packed_index", "pcc_packed_cell", "pcc_cells_host",
     "pcc_tile_order_host", "pcc_cells_device", "pcc_autotune", "pcc_device_cus",
+    "pcc_autotune_default_count", "pcc_tile_arith",
 ]
 
 
@@ -505,7 +508,13 @@ def cells_device(m: int, diag: bool, J0: int, count: int, stream=None):
     return y, x
 
 
-AUTOTUNE_DEFAULT_CANDIDATES = 10
+AUTOTUNE_DEFAULT_CANDIDATES = _lib.pcc_autotune_default_count()
+
+
+def tile_arith(zd: ZDesc) -> int:
+    """The arithmetic the tile kernels use for layout zd (a MODES value):
+    zd.mode, except FP32 for the split layout of rows of at most 64 samples."""
+    return _lib.pcc_tile_arith(ctypes.byref(zd))
 
 
 def autotune(z, zd: ZDesc, r=None, cands: Optional[Sequence[TileCfg]] = None, reps: int = 3,

@@ -88,7 +88,7 @@ int grid_for(const pcc_zdesc &zd, const pcc_tile_cfg &cfg, int epi, int64_t ny =
   int64_t g = cfg.grid;
   if (g == 0) {
     const int cus = device_cus();
-    int occ = tile_occupancy(zd.mode, cfg.tile, epi);
+    int occ = tile_occupancy(arith_mode(zd), cfg.tile, epi);
     if (occ < 1) occ = 1;
     g = (int64_t)(cus > 0 ? cus : 256) * occ;
   }
@@ -98,6 +98,17 @@ int grid_for(const pcc_zdesc &zd, const pcc_tile_cfg &cfg, int epi, int64_t ny =
 }
 
 pcc_status hip_status(hipError_t e) { return note_hip(e) == hipSuccess ? PCC_OK : PCC_E_HIP; }
+
+// pcc_autotune's built-in candidates: both tile sizes, each in the paper's
+// row order and in bands of 2, 4, 8 and 16 tile rows.
+std::vector<pcc_tile_cfg> default_candidates() {
+  std::vector<pcc_tile_cfg> list;
+  for (int tile : {256, 128}) {
+    list.push_back(pcc_tile_cfg{tile, 0, 1, 0});
+    for (int b : {2, 4, 8, 16}) list.push_back(pcc_tile_cfg{tile, 1, b, 0});
+  }
+  return list;
+}
 
 thread_local hipError_t g_last_hip = hipSuccess;
 
@@ -471,6 +482,13 @@ pcc_status pcc_cells_device(int64_t m, int32_t diag, int64_t J0, int64_t count, 
 
 int32_t pcc_device_cus(void) { return device_cus(); }
 
+int32_t pcc_autotune_default_count(void) { return (int32_t)default_candidates().size(); }
+
+int32_t pcc_tile_arith(const pcc_zdesc *zd) {
+  if (check_zdesc(zd) != PCC_OK) return -1;
+  return arith_mode(*zd);
+}
+
 pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_tile_cfg *cands,
                         int32_t ncands, int32_t reps, pcc_tile_cfg *best, float *times_ms,
                         void *stream) {
@@ -478,16 +496,10 @@ pcc_status pcc_autotune(const pcc_zdesc *zd, const void *z, float *r, const pcc_
   if (s != PCC_OK) return s;
   if (!z || !r || !best || reps < 1 || ncands < 0 || (ncands > 0 && !cands)) return PCC_E_ARG;
   std::vector<pcc_tile_cfg> list;
-  if (ncands > 0) {
+  if (ncands > 0)
     list.assign(cands, cands + ncands);
-  } else {
-    const int bands[] = {1, 2, 4, 8, 16};
-    for (int tile : {256, 128}) {
-      list.push_back(pcc_tile_cfg{tile, 0, 1, 0});
-      for (int b : bands)
-        if (b > 1) list.push_back(pcc_tile_cfg{tile, 1, b, 0});
-    }
-  }
+  else
+    list = default_candidates();
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0, e1;
   if (note_hip(hipEventCreate(&e0)) != hipSuccess) return PCC_E_HIP;

@@ -104,6 +104,27 @@ __device__ __forceinline__ void batch_row(const TIn *xr, int64_t l, int64_t l_pa
       xr, l, l_pad, zr, nullptr, nullptr, out_scale, lanes);
 }
 
+// Row `row` (< n) of dataset d, by input type and alignment.
+template <int MODE>
+__device__ __forceinline__ void batch_dataset_row(const BatchDesc &d, int64_t row,
+                                                  unsigned char *zr, int lanes) {
+  if (d.xt == PCC_IN_F64) {
+    const double *xr = (const double *)d.x + row * d.ldx;
+    const bool vec = (d.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
+    if (vec)
+      batch_row<double, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+    else
+      batch_row<double, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+  } else {
+    const float *xr = (const float *)d.x + row * d.ldx;
+    const bool vec = (d.ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
+    if (vec)
+      batch_row<float, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+    else
+      batch_row<float, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void batch_norm_kernel(const BatchDesc *__restrict__ descs,
                                                          const int64_t *__restrict__ grp0s, int D,
@@ -123,21 +144,12 @@ __global__ __launch_bounds__(256) void batch_norm_kernel(const BatchDesc *__rest
       zero_row(zr, d.row_bytes, lanes);
       continue;
     }
-    if (d.xt == PCC_IN_F64) {
-      const double *xr = (const double *)d.x + row * d.ldx;
-      const bool vec = (d.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
-      if (vec)
-        batch_row<double, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
-      else
-        batch_row<double, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
-    } else {
-      const float *xr = (const float *)d.x + row * d.ldx;
-      const bool vec = (d.ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
-      if (vec)
-        batch_row<float, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
-      else
-        batch_row<float, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
-    }
+    // a split dataset of short rows holds FP32 z, as the single-matrix
+    // transformation writes it
+    if (MODE == PCC_SPLIT_BF16X3 && d.l_pad <= kSplitFp32MaxLPad)
+      batch_dataset_row<PCC_FP32>(d, row, zr, lanes);
+    else
+      batch_dataset_row<MODE>(d, row, zr, lanes);
   }
 }
 
@@ -164,7 +176,12 @@ __global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const Batch
     ZView zv{d.z, d.row_bytes, d.n, d.nchunks, d.scale, d.z, d.n};
     EpiArgs ea{};
     ea.r = d.r;
-    do_tile<MODE, TILE, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+    // short split rows hold FP32 z (same LDS layout, so no wait between the
+    // two kinds of tile)
+    if (MODE == PCC_SPLIT_BF16X3 && d.nchunks * 32 <= kSplitFp32MaxLPad)
+      do_tile<PCC_FP32, TILE, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+    else
+      do_tile<MODE, TILE, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
     // do_tile begins with a barrier, which every thread reaches after it has
     // read jslot, so thread 0 may overwrite jslot at the next iteration.
   }

@@ -77,7 +77,8 @@ hipError_t launch_norm(const TIn *x, int64_t ldx, const pcc_zdesc &zd, void *z, 
 template <typename TIn>
 hipError_t dispatch_mode(const TIn *x, int64_t ldx, const pcc_zdesc &zd, void *z, double *stats,
                          int32_t *ndeg, hipStream_t st) {
-  switch (zd.mode) {
+  // a split layout of short rows holds FP32 z (its tiles compute in FP32)
+  switch (arith_mode(zd)) {
     case PCC_FP32: return launch_norm<TIn, PCC_FP32>(x, ldx, zd, z, stats, ndeg, st);
     case PCC_SPLIT_BF16X3: return launch_norm<TIn, PCC_SPLIT_BF16X3>(x, ldx, zd, z, stats, ndeg, st);
     case PCC_BF16: return launch_norm<TIn, PCC_BF16>(x, ldx, zd, z, stats, ndeg, st);

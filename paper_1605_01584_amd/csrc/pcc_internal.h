@@ -121,4 +121,21 @@ inline int kchunk_of(int mode) {
   return (mode == PCC_FP32 || mode == PCC_SPLIT_BF16X3) ? 32 : 64;
 }
 
+// Arithmetic of the split-BF16 layout on short rows.  Two BF16 terms carry z
+// to about 2^-16 relative and the lo.lo product is dropped, so a product
+// z_i[k] z_j[k] is off by up to 3 * 2^-16 |z_i[k] z_j[k]|; over many samples
+// these errors have random signs and average out, over a handful they do not
+// (|dr| above 1e-5 at l <= 8 on Gaussian rows).  Rows of at most two chunks
+// (l_pad <= 64) therefore hold z in FP32 and are contracted on FP32 MFMA:
+// the FP32 and split layouts both pack 32 samples into a 128-byte chunk, so
+// the row size is the same and only the arithmetic changes.  At such l a
+// tile does 2 l flops per pair against 4 bytes of r stored, so the FP32
+// tiles cost about what the split ones do.
+constexpr int64_t kSplitFp32MaxLPad = 64;
+
+inline int arith_mode(int mode, int64_t l_pad) {
+  return (mode == PCC_SPLIT_BF16X3 && l_pad <= kSplitFp32MaxLPad) ? (int)PCC_FP32 : mode;
+}
+inline int arith_mode(const pcc_zdesc &zd) { return arith_mode(zd.mode, zd.l_pad); }
+
 }  // namespace pcc

@@ -396,7 +396,7 @@ hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *pe
   const int64_t jobs = mb * (mb + 1) / 2;
   const size_t lds = lds_bytes(zd.l_pad);
   const bool aligned = (zd.l % 4) == 0 && ((reinterpret_cast<uintptr_t>(perms) & 15) == 0);
-  const bool split = zd.mode == PCC_SPLIT_BF16X3;
+  const bool split = arith_mode(zd) == PCC_SPLIT_BF16X3;
   const void *k;
   int threads;
   if (split) {

@@ -203,7 +203,7 @@ hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const p
                            int grid, hipStream_t st) {
   UniformArgs a = make_args(zd, z, cfg);
   a.ea.r = r;
-  return launch(zd.mode, a, cfg.tile, EPI_PACKED, grid, st);
+  return launch(arith_mode(zd), a, cfg.tile, EPI_PACKED, grid, st);
 }
 
 // Tile ids [j0, j1) of the symmetric schedule, r holding the packed
@@ -217,14 +217,14 @@ hipError_t launch_allpairs_range(const pcc_zdesc &zd, const void *z, float *r, i
   a.ea.roff = roff;
   a.j0 = j0;
   a.njobs = j1;
-  return launch(zd.mode, a, cfg.tile, EPI_PACKED, grid, st);
+  return launch(arith_mode(zd), a, cfg.tile, EPI_PACKED, grid, st);
 }
 
 hipError_t launch_allpairs_f64(const pcc_zdesc &zd, const void *z, double *r,
                                const pcc_tile_cfg &cfg, int grid, hipStream_t st) {
   UniformArgs a = make_args(zd, z, cfg);
   a.ea.r64 = r;
-  return launch(zd.mode, a, cfg.tile, EPI_PACKED_F64, grid, st);
+  return launch(arith_mode(zd), a, cfg.tile, EPI_PACKED_F64, grid, st);
 }
 
 hipError_t launch_edges(const pcc_zdesc &zd, const void *z, float thr, int32_t *ij, float *rv,
@@ -238,7 +238,7 @@ hipError_t launch_edges(const pcc_zdesc &zd, const void *z, float thr, int32_t *
   a.ea.rv = rv;
   a.ea.cap = cap;
   a.ea.count = (unsigned long long *)count;
-  return launch(zd.mode, a, cfg.tile, EPI_EDGES, grid, st);
+  return launch(arith_mode(zd), a, cfg.tile, EPI_EDGES, grid, st);
 }
 
 hipError_t launch_allpairs_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &zdy,
@@ -247,7 +247,7 @@ hipError_t launch_allpairs_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zd
   UniformArgs a = make_args_xy(zdx, zx, zdy, zy, cfg);
   a.ea.r = r;
   a.ea.ldr = ldr;
-  return launch(zdx.mode, a, cfg.tile, EPI_RECT, grid, st);
+  return launch(arith_mode(zdx), a, cfg.tile, EPI_RECT, grid, st);
 }
 
 hipError_t launch_edges_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc &zdy,
@@ -261,7 +261,7 @@ hipError_t launch_edges_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc
   a.ea.rv = rv;
   a.ea.cap = cap;
   a.ea.count = (unsigned long long *)count;
-  return launch(zdx.mode, a, cfg.tile, EPI_RECT_EDGES, grid, st);
+  return launch(arith_mode(zdx), a, cfg.tile, EPI_RECT_EDGES, grid, st);
 }
 
 hipError_t launch_cells(int64_t m, int diag, int64_t J0, int64_t count, int64_t *y, int64_t *x,

@@ -2,8 +2,8 @@
 
 * ``best_cfg(n, l, mode)``: the fastest ``TileCfg`` for an all-pairs run of
   that shape, measured by ``pcc_autotune`` (HIP events, median of reps) on a
-  synthetic Z of the same shape (run time does not depend on the values),
-  cached per (device, mode, n bucket, l bucket).
+  synthetic Z of exactly that shape (run time does not depend on the
+  values), cached per (device, mode, n, l_pad).
 * ``tune_batch(xs, mode)``: the fastest per-dataset tile sizes for one
   uneven batch.  Candidate assignments (all 256, all 128, and "128 below a
   size threshold" rules) are built as batch plans and timed as whole graph
@@ -56,14 +56,6 @@ def _device_key() -> str:
     return f"{getattr(props, 'gcnArchName', props.name)}:{props.multi_processor_count}"
 
 
-def _bucket(v: int) -> int:
-    """Power-of-two bucket (shapes within a factor 2 share an entry)."""
-    b = 1
-    while b < v:
-        b <<= 1
-    return b
-
-
 def candidates() -> List[pcc.TileCfg]:
     out = []
     for tile in (256, 128):
@@ -73,17 +65,27 @@ def candidates() -> List[pcc.TileCfg]:
     return out
 
 
-def best_cfg(n: int, l: int, mode="split", reps: int = 3, use_cache: bool = True) -> pcc.TileCfg:
+def best_cfg(n: int, l: int, mode="split", reps: int = 3, use_cache: bool = True,
+             r=None) -> pcc.TileCfg:
+    """Fastest schedule for n profiles of l samples.  Timed at that very
+    shape (the tile count and the band balance depend on n, the per-tile
+    work on l_pad), on random data; r (nullable) is an n(n-1)/2 float32
+    device buffer to time into, e.g. the caller's own output."""
     mode_i = pcc._mode(mode)
-    key = f"allpairs|{_device_key()}|{mode_i}|{_bucket(n)}|{_bucket(l)}"
+    zd = pcc.z_layout(n, l, mode_i)
+    key = f"allpairs|{_device_key()}|{mode_i}|n={n}|lpad={zd.l_pad}"
     cache = _load() if use_cache else {}
     if key in cache:
         return pcc.TileCfg(*cache[key]["cfg"])
     import torch
-    nb, lb = _bucket(n), _bucket(l)
-    x = torch.randn(nb, lb, device="cuda", dtype=torch.float32)
-    z, zd = pcc.normalize(x, mode)
-    r = torch.empty(nb * (nb - 1) // 2, dtype=torch.float32, device="cuda")
+    x = torch.randn(n, l, device="cuda", dtype=torch.float32)
+    z, zd = pcc.normalize(x, mode_i)
+    del x
+    npairs = n * (n - 1) // 2
+    if r is None:
+        r = torch.empty(npairs, dtype=torch.float32, device="cuda")
+    elif r.numel() < npairs or r.dtype != torch.float32 or not r.is_cuda:
+        raise ValueError("r must be a device float32 tensor of n(n-1)/2")
     cands = candidates()
     best, times = pcc.autotune(z, zd, r, cands, reps=reps)
     if use_cache:

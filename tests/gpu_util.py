@@ -15,6 +15,15 @@ def packed_pos(n: int, I, J) -> np.ndarray:
     return packed_start(n)[I] + (J - I - 1)
 
 
+# The split layout of rows of at most two 128-byte chunks holds FP32 z (the
+# rows the split arithmetic would not hold to 1e-5 are computed in FP32).
+SPLIT_FP32_MAX_LPAD = 64
+
+
+def split_is_fp32(zd) -> bool:
+    return zd.mode == 1 and zd.l_pad <= SPLIT_FP32_MAX_LPAD
+
+
 def bf16_to_f32(u16: np.ndarray) -> np.ndarray:
     return (u16.astype(np.uint32) << 16).view(np.float32)
 
@@ -24,7 +33,7 @@ def decode_z(zbytes: np.ndarray, zd) -> dict:
     kernels multiply, FP16 unscaled), plus 'hi'/'lo' for the split layout."""
     n_pad, l_pad, rb, mode = zd.n_pad, zd.l_pad, zd.row_bytes, zd.mode
     raw = np.asarray(zbytes, dtype=np.uint8)[: n_pad * rb].reshape(n_pad, rb)
-    if mode == 0:  # FP32
+    if mode == 0 or (mode == 1 and l_pad <= SPLIT_FP32_MAX_LPAD):  # FP32
         v = raw.view(np.float32).astype(np.float64)
         return {"value": v}
     if mode == 4:  # FP64

@@ -247,3 +247,29 @@ def test_one_hip_runtime_whatever_the_import_order():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_tile_arith_routes_short_split_rows_to_fp32():
+    """Split layouts of rows of one or two chunks (l_pad <= 64) compute in
+    FP32; every other layout computes in its own mode."""
+    import paper_1605_01584_amd as pcc
+    for l, want in [(2, pcc.FP32), (32, pcc.FP32), (33, pcc.FP32), (64, pcc.FP32),
+                    (65, pcc.SPLIT_BF16X3), (4096, pcc.SPLIT_BF16X3)]:
+        assert pcc.tile_arith(pcc.z_layout(100, l, "split")) == want, l
+    for mode in ("fp32", "bf16", "fp16", "fp64"):
+        for l in (2, 64, 65, 4096):
+            assert pcc.tile_arith(pcc.z_layout(100, l, mode)) == pcc.MODES[mode]
+    # the split layout of short rows is byte-compatible with the FP32 one
+    for l in (2, 33, 64):
+        a, b = pcc.z_layout(300, l, "split"), pcc.z_layout(300, l, "fp32")
+        assert (a.row_bytes, a.l_pad, a.bytes) == (b.row_bytes, b.l_pad, b.bytes)
+    bad = pcc.z_layout(10, 10, "fp32")
+    bad.row_bytes += 128
+    assert pcc._lib.pcc_tile_arith(ctypes.byref(bad)) == -1
+
+
+def test_autotune_default_count():
+    import paper_1605_01584_amd as pcc
+    from paper_1605_01584_amd import tune
+    assert pcc.AUTOTUNE_DEFAULT_CANDIDATES == pcc._lib.pcc_autotune_default_count() == 10
+    assert len(tune.candidates()) == 10

@@ -15,13 +15,13 @@ from gpu_util import packed_pos, to_device
 pytestmark = pytest.mark.gpu
 
 BAND = 1e-6
-# split's tolerance on r: 1e-5 from a few dozen samples on; below, the
-# worst case 3 * 2^-16 of the two-term split (see the all-pairs tests)
-SPLIT_WORST = 3 * 2.0 ** -16 + 1e-6
+# split's tolerance on r, 1e-5 at every l (rows of at most 64 samples are
+# computed in FP32 arithmetic in the split layout)
+SPLIT_TOL = 1e-5
 
 
 def split_band(l):
-    return 2 * (1e-5 if l >= 63 else SPLIT_WORST)
+    return 2 * SPLIT_TOL
 
 
 def _gpu_counts(X, perms, mode="fp32"):

@@ -11,15 +11,12 @@ from gpu_util import to_device
 
 pytestmark = pytest.mark.gpu
 
-SPLIT_WORST = 3 * 2.0 ** -16 + 1e-6
 LOOSE = {"bf16": 6e-3, "fp16": 1.5e-3}
 
 
 def tol_for(mode, l):
     if mode == "fp64":
         return (2 * l + 64) * 2.0 ** -53 + 2.0 ** -24      # FP32 output
-    if mode == "split" and l < 63:
-        return SPLIT_WORST
     return LOOSE.get(mode, 1e-5)
 
 
