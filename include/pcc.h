@@ -6,7 +6,8 @@
  * to void* (NULL means the default stream).  The caller owns every buffer.
  * No entry point allocates device memory while computing; the only device
  * allocations the library ever makes are the hipGraph objects of a batch
- * plan (pcc_batch_plan_create).
+ * plan (pcc_batch_plan_create).  pcc_batch_run_noalloc uses a file-scope
+ * device array of the library as its scratch.
  *
  * Method (Liu, Pan and Aluru, "Parallel pairwise correlation computation on
  * Intel Xeon Phi clusters"):
@@ -337,6 +338,34 @@ pcc_status pcc_batch_plan_launch(pcc_batch_plan *plan, void *stream);
 /* Total tile jobs of the plan (for accounting). */
 int64_t pcc_batch_plan_jobs(const pcc_batch_plan *plan);
 pcc_status pcc_batch_plan_destroy(pcc_batch_plan *plan);
+
+/* Most datasets one pcc_batch_run_noalloc call takes. */
+#define PCC_BATCH_NOALLOC_MAX_D 256
+
+/* The uneven batch of a plan, run directly, with no allocation at all: for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Computes exactly
+ * what a plan of the same items and mode computes when launched (same
+ * kernels, same job order: bit-identical z and r), asynchronously on
+ * `stream`, without creating a graph or a workspace.
+ *   items  as for pcc_batch_plan_create; the caller passes every input and
+ *          output buffer.  Need only stay valid until the call returns (the
+ *          descriptors travel as kernel arguments).
+ *   D      1 <= D <= PCC_BATCH_NOALLOC_MAX_D; a larger D gives PCC_E_SHAPE.
+ * Scratch: the descriptor table and the job counters live in a file-scope
+ * device array of the library (about 39 KB; each GPU the library runs on
+ * holds its own copy until the process ends).  Its address is looked up on
+ * the first call on a device, so make that first call outside stream
+ * capture.  Every call on one GPU shares that array and rewrites it (the
+ * counters are zeroed by a kernel, not by a memset): calls that overlap on
+ * one GPU (two streams, two threads, two captured graphs replayed at once)
+ * race and may skip or repeat tiles, so order them (one stream, or events).
+ * Launches kernels only: no hipMalloc, hipFree, memcpy or memset, so the
+ * call can be recorded under stream capture.  Errors: PCC_E_ARG / _MODE /
+ * _SHAPE for the arguments (nothing launched), PCC_E_HIP for a failed
+ * launch. */
+pcc_status pcc_batch_run_noalloc(int32_t D, const pcc_batch_item *items, pcc_mode_t mode,
+                                 void *stream);
 
 /* ---- Job maps, host side, for tests and tooling -------------------------
  * Inclusive map over an m x m triangle (diagonal counted in), Eq. (9)-(15):

@@ -113,6 +113,7 @@ _sig("pcc_batch_plan_create", _i32, _i32, ctypes.POINTER(BatchItem), _i32, _vp, 
 _sig("pcc_batch_plan_launch", _i32, _vp, _vp)
 _sig("pcc_batch_plan_jobs", _i64, _vp)
 _sig("pcc_batch_plan_destroy", _i32, _vp)
+_sig("pcc_batch_run_noalloc", _i32, _i32, ctypes.POINTER(BatchItem), _i32, _vp)
 _sig("pcc_job_of_cell", _i64, _i64, _i64, _i64)
 _sig("pcc_cell_of_job", None, _i64, _i64, _i64p, _i64p)
 _sig("pcc_packed_index", _i64, _i64, _i64, _i64)
@@ -136,8 +137,10 @@ EXPORTED = [
     "pcc_batch_plan_launch", "pcc_batch_plan_jobs", "pcc_batch_plan_destroy", "pcc_job_of_cell",
     "pcc_cell_of_job", "pcc_packed_index", "pcc_packed_cell", "pcc_cells_host",
     "pcc_tile_order_host", "pcc_cells_device", "pcc_autotune", "pcc_device_cus",
-    "pcc_autotune_default_count", "pcc_tile_arith",
+    "pcc_autotune_default_count", "pcc_tile_arith", "pcc_batch_run_noalloc",
 ]
+
+BATCH_NOALLOC_MAX_D = 256  # PCC_BATCH_NOALLOC_MAX_D
 
 
 class PccError(RuntimeError):
@@ -443,6 +446,48 @@ def permtest(z, zd: ZDesc, perms, out=None, stream=None, validate: bool = True):
     return out
 
 
+def _batch_items(xs, mode: int, tiles=None, zs=None, rs=None):
+    """BatchItem array for datasets xs, with z and r buffers (given or new)."""
+    torch = _torch()
+    D = len(xs)
+    items = (BatchItem * D)()
+    zds, zo, ro = [], [], []
+    for d, x in enumerate(xs):
+        if x.dim() != 2 or x.stride(1) != 1:
+            raise ValueError("each x must be 2-D with unit stride along samples")
+        n, l = x.shape
+        zd = z_layout(n, l, mode)
+        z = zs[d] if zs is not None else torch.empty(zd.bytes, dtype=torch.uint8, device=x.device)
+        r = rs[d] if rs is not None else torch.empty(n * (n - 1) // 2, dtype=torch.float32,
+                                                      device=x.device)
+        if z.numel() * z.element_size() < zd.bytes or r.numel() < n * (n - 1) // 2 \
+                or r.dtype != torch.float32:
+            raise ValueError(f"dataset {d}: z or r too small")
+        zds.append(zd)
+        zo.append(z)
+        ro.append(r)
+        items[d] = BatchItem(x.data_ptr(), x.stride(0), n, l,
+                             IN_F64 if x.dtype == torch.float64 else IN_F32,
+                             int(tiles[d]) if tiles is not None else 0,
+                             _dev_ptr(z, "z").value, _dev_ptr(r, "r").value)
+    return items, zds, zo, ro
+
+
+def batch_run_noalloc(xs: Sequence, mode="split", tiles: Optional[Sequence[int]] = None,
+                      zs=None, rs=None, stream=None):
+    """The batch of BatchPlan(xs, mode, tiles) run by pcc_batch_run_noalloc:
+    no graph and no workspace (the library's static scratch).  zs / rs:
+    optional output buffers (new ones otherwise).  Returns (zd, z, r) lists."""
+    torch = _torch()
+    if len(xs) > BATCH_NOALLOC_MAX_D:
+        raise ValueError(f"at most {BATCH_NOALLOC_MAX_D} datasets")
+    md = _mode(mode)
+    items, zds, zo, ro = _batch_items(list(xs), md, tiles, zs, rs)
+    _check(_lib.pcc_batch_run_noalloc(len(xs), items, md, _stream(torch, stream)),
+           "pcc_batch_run_noalloc")
+    return zds, zo, ro
+
+
 class BatchPlan:
     """One hipGraph running the transformation and all pairs of D datasets.
 
@@ -455,22 +500,7 @@ class BatchPlan:
         self.D = len(xs)
         self.mode = _mode(mode)
         self.xs = list(xs)
-        self.zd, self.z, self.r = [], [], []
-        items = (BatchItem * self.D)()
-        for d, x in enumerate(self.xs):
-            if x.dim() != 2 or x.stride(1) != 1:
-                raise ValueError("each x must be 2-D with unit stride along samples")
-            n, l = x.shape
-            zd = z_layout(n, l, self.mode)
-            z = torch.empty(zd.bytes, dtype=torch.uint8, device=x.device)
-            r = torch.empty(n * (n - 1) // 2, dtype=torch.float32, device=x.device)
-            self.zd.append(zd)
-            self.z.append(z)
-            self.r.append(r)
-            items[d] = BatchItem(x.data_ptr(), x.stride(0), n, l,
-                                 IN_F64 if x.dtype == torch.float64 else IN_F32,
-                                 int(tiles[d]) if tiles is not None else 0,
-                                 z.data_ptr(), r.data_ptr())
+        items, self.zd, self.z, self.r = _batch_items(self.xs, self.mode, tiles)
         self._items = items
         ws = _lib.pcc_batch_workspace_size(self.D)
         self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.xs[0].device)

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "norm_core.h"
@@ -55,7 +56,17 @@ constexpr int kCounterStride = 16;  // the two job counters, 128 bytes apart
 // global loads; larger batches search the compact key array in place.
 constexpr int kKeysInLds = 1024;
 
-inline size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+constexpr size_t batch_ws_bytes(int32_t D) {
+  return kCounterBytes + round256((size_t)D * sizeof(BatchDesc)) +
+         2 * round256((size_t)D * sizeof(int64_t));
+}
+
+// Datasets of one pcc_batch_run_noalloc call, and the size of its static
+// scratch (their workspace).
+constexpr int32_t kStaticMaxD = PCC_BATCH_NOALLOC_MAX_D;
+constexpr size_t kStaticScratchBytes = batch_ws_bytes(kStaticMaxD);
 
 // Whole workgroup; returns the keys to search (LDS copy or global array).
 __device__ __forceinline__ const int64_t *load_keys(const int64_t *__restrict__ gkeys, int D,
@@ -233,31 +244,24 @@ hipError_t launch_batch(const BatchDesc *descs, const int64_t *job0s, const int6
 
 using namespace pcc;
 
-struct pcc_batch_plan {
-  int32_t D;
-  int32_t mode;
-  int64_t jobs;
-  int64_t rows;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
+namespace pcc {
+namespace {
+
+// Totals of a batch after build_batch.
+struct BatchSums {
+  int64_t jobs256, jobs128, groups, rows;
+  int d256;  // datasets [0, d256) use 256-wide tiles
 };
 
-extern "C" {
-
-size_t pcc_batch_workspace_size(int32_t D) {
-  if (D < 0) return 0;
-  return kCounterBytes + round256((size_t)D * sizeof(BatchDesc)) +
-         2 * round256((size_t)D * sizeof(int64_t));
-}
-
-pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mode_t mode,
-                                 void *workspace, size_t workspace_bytes, void *stream,
-                                 pcc_batch_plan **plan) {
-  if (!plan || D < 1 || !items) return PCC_E_ARG;
-  *plan = nullptr;
-  if (mode < PCC_FP32 || mode > PCC_FP16) return PCC_E_MODE;
-  if (!workspace || workspace_bytes < pcc_batch_workspace_size(D)) return PCC_E_WORKSPACE;
-  std::vector<BatchDesc> ds((size_t)D);
+// Host work of a batch: validate the items, fill one descriptor per dataset,
+// order them (256-wide tiles first, one kernel each; longest jobs first
+// within a group: the work of one job grows with l_pad for a given tile) and
+// give each its first job, row and row group.  ds holds D descriptors.
+// Stable ordering, by insertion for the few datasets of a call that may not
+// allocate and by std::stable_sort otherwise: either way the order is the
+// one the comparison fixes, so both entry points build the same table.
+pcc_status build_batch(int32_t D, const pcc_batch_item *items, pcc_mode_t mode, BatchDesc *ds,
+                       BatchSums *sums) {
   for (int32_t k = 0; k < D; ++k) {
     const pcc_batch_item &it = items[k];
     if (!it.x || !it.z || !it.r) return PCC_E_ARG;
@@ -273,7 +277,7 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
       tile = c.tile;
     }
     if (tile != 128 && tile != 256) return PCC_E_ARG;
-    BatchDesc &d = ds[(size_t)k];
+    BatchDesc &d = ds[k];
     memset(&d, 0, sizeof(d));
     d.x = it.x;
     d.ldx = it.ldx;
@@ -292,40 +296,171 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
     d.scale = (mode == PCC_FP16) ? (float)(1.0 / (double)zd.l) : 1.0f;
     d.out_scale = (mode == PCC_FP16) ? sqrt((double)zd.l) : 1.0;
   }
-  // 256-wide datasets first, then 128-wide ones (one kernel each); longest
-  // jobs first within a group (work of one job ~ l_pad for a given tile).
-  std::stable_sort(ds.begin(), ds.end(), [](const BatchDesc &a, const BatchDesc &b) {
+  const auto before = [](const BatchDesc &a, const BatchDesc &b) {
     if (a.tile != b.tile) return a.tile > b.tile;
     return a.l_pad > b.l_pad;
-  });
-  int64_t jobs256 = 0, jobs128 = 0, rows = 0, groups = 0;
-  int d256 = 0;
-  for (BatchDesc &d : ds) {
-    int64_t &jobs = (d.tile == 256) ? jobs256 : jobs128;
-    if (d.tile == 256) ++d256;
-    d.job0 = jobs;
-    d.row0 = rows;
-    d.grp0 = groups;
-    jobs += d.m * (d.m + 1) / 2;
-    rows += d.n_pad;
-    groups += d.n_pad / (64 / d.lanes);  // n_pad is a multiple of 256
+  };
+  if (D <= kStaticMaxD) {
+    for (int32_t k = 1; k < D; ++k) {
+      const BatchDesc v = ds[k];
+      int32_t j = k;
+      for (; j > 0 && before(v, ds[j - 1]); --j) ds[j] = ds[j - 1];
+      ds[j] = v;
+    }
+  } else {
+    std::stable_sort(ds, ds + D, before);
   }
-  const int64_t jobs = jobs256 + jobs128;
+  BatchSums t{0, 0, 0, 0, 0};
+  for (int32_t k = 0; k < D; ++k) {
+    BatchDesc &d = ds[k];
+    int64_t &jobs = (d.tile == 256) ? t.jobs256 : t.jobs128;
+    if (d.tile == 256) ++t.d256;
+    d.job0 = jobs;
+    d.row0 = t.rows;
+    d.grp0 = t.groups;
+    jobs += d.m * (d.m + 1) / 2;
+    t.rows += d.n_pad;
+    t.groups += d.n_pad / (64 / d.lanes);  // n_pad is a multiple of 256
+  }
+  *sums = t;
+  return PCC_OK;
+}
+
+// Descriptor table of a call that may not allocate: written into the
+// static scratch by kernels that take the descriptors as arguments, so the
+// call records no copy or fill node under stream capture.
+constexpr int kDescsPerUpload = 8;
+struct DescUpload {
+  BatchDesc d[kDescsPerUpload];
+};
+
+__global__ void batch_upload_kernel(DescUpload u, int first, int count, BatchDesc *descs,
+                                    int64_t *job0s, int64_t *grp0s) {
+  const int k = threadIdx.x;
+  if (k < count) {
+    descs[first + k] = u.d[k];
+    job0s[first + k] = u.d[k].job0;
+    grp0s[first + k] = u.d[k].grp0;
+  }
+}
+
+template <int MODE>
+hipError_t launch_batch_mode(const BatchDesc *descs, const int64_t *job0s, const int64_t *grp0s,
+                             int D, const BatchSums &t, unsigned long long *counters, int cus,
+                             hipStream_t st) {
+  return launch_batch<MODE>(descs, job0s, grp0s, D, t.d256, t.groups, t.jobs256, t.jobs128,
+                            counters, cus, st);
+}
+
+hipError_t launch_batch_any(int mode, const BatchDesc *descs, const int64_t *job0s,
+                            const int64_t *grp0s, int D, const BatchSums &t,
+                            unsigned long long *counters, int cus, hipStream_t st) {
+  switch (mode) {
+    case PCC_FP32: return launch_batch_mode<PCC_FP32>(descs, job0s, grp0s, D, t, counters, cus, st);
+    case PCC_SPLIT_BF16X3:
+      return launch_batch_mode<PCC_SPLIT_BF16X3>(descs, job0s, grp0s, D, t, counters, cus, st);
+    case PCC_BF16: return launch_batch_mode<PCC_BF16>(descs, job0s, grp0s, D, t, counters, cus, st);
+    case PCC_FP16: return launch_batch_mode<PCC_FP16>(descs, job0s, grp0s, D, t, counters, cus, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Workspace layout: [job counters | descriptor table | job0 keys | grp0 keys].
+struct WsParts {
+  unsigned long long *counters;
+  BatchDesc *descs;
+  int64_t *job0s, *grp0s;
+};
+
+WsParts ws_parts(void *ws, int32_t D) {
+  unsigned char *b = (unsigned char *)ws;
+  WsParts p;
+  p.counters = (unsigned long long *)b;
+  p.descs = (BatchDesc *)(b + kCounterBytes);
+  p.job0s = (int64_t *)(b + kCounterBytes + round256((size_t)D * sizeof(BatchDesc)));
+  p.grp0s = (int64_t *)((unsigned char *)p.job0s + round256((size_t)D * sizeof(int64_t)));
+  return p;
+}
+
+// Scratch of pcc_batch_run_noalloc: the workspace of kStaticMaxD datasets in
+// a file-scope device array.  Host code never passes this name to a kernel
+// (on the host it is only a stand-in for the symbol): the device address
+// comes from hipGetSymbolAddress, once per device, and is kept per device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on the current device.  Two threads may both
+// look it up on a first call; they store the same address.
+hipError_t scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void *p = g_scratch_addr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev].store(p, std::memory_order_release);
+  }
+  *out = p;
+  return hipSuccess;
+}
+
+int device_cus_or(int fallback) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    return fallback;
+  return cus;
+}
+
+}  // namespace
+}  // namespace pcc
+
+struct pcc_batch_plan {
+  int32_t D;
+  int32_t mode;
+  int64_t jobs;
+  int64_t rows;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+size_t pcc_batch_workspace_size(int32_t D) {
+  if (D < 0) return 0;
+  return batch_ws_bytes(D);
+}
+
+pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mode_t mode,
+                                 void *workspace, size_t workspace_bytes, void *stream,
+                                 pcc_batch_plan **plan) {
+  if (!plan || D < 1 || !items) return PCC_E_ARG;
+  *plan = nullptr;
+  if (mode < PCC_FP32 || mode > PCC_FP16) return PCC_E_MODE;
+  if (!workspace || workspace_bytes < pcc_batch_workspace_size(D)) return PCC_E_WORKSPACE;
+  std::vector<BatchDesc> ds((size_t)D);
+  BatchSums t;
+  const pcc_status bs = build_batch(D, items, mode, ds.data(), &t);
+  if (bs != PCC_OK) return bs;
+  const int64_t jobs = t.jobs256 + t.jobs128;
   hipStream_t st = (hipStream_t)stream;
-  unsigned char *ws = (unsigned char *)workspace;
-  BatchDesc *ddesc = (BatchDesc *)(ws + kCounterBytes);
-  int64_t *djob0 = (int64_t *)(ws + kCounterBytes + round256((size_t)D * sizeof(BatchDesc)));
-  int64_t *dgrp0 = (int64_t *)((unsigned char *)djob0 + round256((size_t)D * sizeof(int64_t)));
+  const WsParts wp = ws_parts(workspace, D);
   std::vector<int64_t> keys(2 * (size_t)D);
   for (int32_t k = 0; k < D; ++k) {
     keys[(size_t)k] = ds[(size_t)k].job0;
     keys[(size_t)D + k] = ds[(size_t)k].grp0;
   }
-  if (note_hip(hipMemcpyAsync(ddesc, ds.data(), ds.size() * sizeof(BatchDesc),
+  if (note_hip(hipMemcpyAsync(wp.descs, ds.data(), ds.size() * sizeof(BatchDesc),
                               hipMemcpyHostToDevice, st)) != hipSuccess ||
-      note_hip(hipMemcpyAsync(djob0, keys.data(), (size_t)D * sizeof(int64_t),
+      note_hip(hipMemcpyAsync(wp.job0s, keys.data(), (size_t)D * sizeof(int64_t),
                               hipMemcpyHostToDevice, st)) != hipSuccess ||
-      note_hip(hipMemcpyAsync(dgrp0, keys.data() + D, (size_t)D * sizeof(int64_t),
+      note_hip(hipMemcpyAsync(wp.grp0s, keys.data() + D, (size_t)D * sizeof(int64_t),
                               hipMemcpyHostToDevice, st)) != hipSuccess ||
       note_hip(hipStreamSynchronize(st)) != hipSuccess)
     return PCC_E_HIP;
@@ -340,7 +475,7 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
   p->D = D;
   p->mode = mode;
   p->jobs = jobs;
-  p->rows = rows;
+  p->rows = t.rows;
   hipStream_t cs = nullptr;
   if (note_hip(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
     free(p);
@@ -350,17 +485,8 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
   if (note_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess) {
     rs = PCC_E_HIP;
   } else {
-    unsigned long long *counter = (unsigned long long *)ws;
-    hipError_t e = hipErrorInvalidValue;
-    switch (mode) {
-      case PCC_FP32: e = launch_batch<PCC_FP32>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
-      case PCC_SPLIT_BF16X3:
-        e = launch_batch<PCC_SPLIT_BF16X3>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs);
-        break;
-      case PCC_BF16: e = launch_batch<PCC_BF16>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
-      case PCC_FP16: e = launch_batch<PCC_FP16>(ddesc, djob0, dgrp0, D, d256, groups, jobs256, jobs128, counter, cus, cs); break;
-      default: break;  // refused above
-    }
+    const hipError_t e =
+        launch_batch_any(mode, wp.descs, wp.job0s, wp.grp0s, D, t, wp.counters, cus, cs);
     hipGraph_t g = nullptr;
     (void)note_hip(e);
     const hipError_t e2 = note_hip(hipStreamEndCapture(cs, &g));
@@ -385,6 +511,35 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
   }
   *plan = p;
   return PCC_OK;
+}
+
+pcc_status pcc_batch_run_noalloc(int32_t D, const pcc_batch_item *items, pcc_mode_t mode,
+                                 void *stream) {
+  if (D < 1 || !items) return PCC_E_ARG;
+  if (mode < PCC_FP32 || mode > PCC_FP16) return PCC_E_MODE;
+  if (D > kStaticMaxD) return PCC_E_SHAPE;
+  BatchDesc ds[kStaticMaxD];  // host stack, about 35 KB
+  BatchSums t;
+  const pcc_status bs = build_batch(D, items, mode, ds, &t);
+  if (bs != PCC_OK) return bs;
+  void *sp = nullptr;
+  if (note_hip(scratch_address(&sp)) != hipSuccess) return PCC_E_HIP;
+  const WsParts wp = ws_parts(sp, D);
+  hipStream_t st = (hipStream_t)stream;
+  for (int32_t k0 = 0; k0 < D; k0 += kDescsPerUpload) {
+    DescUpload u;
+    memset(&u, 0, sizeof(u));
+    const int cnt = std::min<int32_t>(kDescsPerUpload, D - k0);
+    for (int k = 0; k < cnt; ++k) u.d[k] = ds[k0 + k];
+    hipLaunchKernelGGL(batch_upload_kernel, dim3(1), dim3(64), 0, st, u, (int)k0, cnt, wp.descs,
+                       wp.job0s, wp.grp0s);
+    if (note_hip(hipGetLastError()) != hipSuccess) return PCC_E_HIP;
+  }
+  // the job counters are zeroed by the batch's first kernel
+  return note_hip(launch_batch_any(mode, wp.descs, wp.job0s, wp.grp0s, D, t, wp.counters,
+                                   device_cus_or(256), st)) == hipSuccess
+             ? PCC_OK
+             : PCC_E_HIP;
 }
 
 pcc_status pcc_batch_plan_launch(pcc_batch_plan *plan, void *stream) {

@@ -124,6 +124,12 @@ def test_host_argument_errors_return_before_launch():
     assert lib.pcc_batch_plan_create(1, items, 9, fake, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_MODE
     assert lib.pcc_batch_plan_launch(None, None) == pcc.PCC_E_ARG
     assert lib.pcc_batch_plan_destroy(None) == pcc.PCC_E_ARG
+    # batch without allocation: too many datasets, none, a bad mode, a null item
+    big = (pcc.BatchItem * (pcc.BATCH_NOALLOC_MAX_D + 1))()
+    assert lib.pcc_batch_run_noalloc(pcc.BATCH_NOALLOC_MAX_D + 1, big, 1, None) == pcc.PCC_E_SHAPE
+    assert lib.pcc_batch_run_noalloc(0, items, 1, None) == pcc.PCC_E_ARG
+    assert lib.pcc_batch_run_noalloc(1, items, pcc.FP64, None) == pcc.PCC_E_MODE
+    assert lib.pcc_batch_run_noalloc(1, items, 1, None) == pcc.PCC_E_ARG
     # maps
     assert lib.pcc_cells_host(10, 1, 50, 10, fake, fake) == pcc.PCC_E_SHAPE
     assert lib.pcc_cells_device(10, 1, 0, 5, None, fake, None) == pcc.PCC_E_ARG
