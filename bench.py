@@ -186,7 +186,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline step only")
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (normalize, fp32, modes16, edges, fp64, xy, to_host, "
-                         "calibration, permtest, batched, big_edges, table1, config1, config2), default all")
+                         "calibration, permtest, permtest_long, batched, big_edges, table1, config1, "
+                         "config2), default all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -465,6 +466,8 @@ def main():
     torch.cuda.empty_cache()
     if want("permtest"):
         extras.update(bench_permtest(pcc, workloads, stream, dev))
+    if want("permtest_long"):
+        extras.update(bench_permtest_long(pcc, workloads, stream, dev))
     if want("batched"):
         extras.update(bench_batched(pcc, workloads, stream, dev))
     if want("big_edges"):
@@ -554,6 +557,37 @@ def bench_permtest(pcc, workloads, stream, dev):
     out["permtest_split"]["vs_fp32_counts"] = {
         "equal_frac": float((d == 0).float().mean()), "max_abs_diff": int(d.max()),
         "speedup": out["permtest"]["ms"] / out["permtest_split"]["ms"]}
+    return out
+
+
+def bench_permtest_long(pcc, workloads, stream, dev):
+    """Permutation test on profiles of the evaluation's length (l = 5000), past
+    the LDS kernel's limit: the tiled form (observed r, then per group of
+    permuted copies one tile launch with a counting epilogue)."""
+    import torch
+    n, l, P = 4096, 5000, 100
+    log(f"[bench] permutation test, long profiles n={n} l={l} P={P} (tiled form)")
+    X, _ = workloads.planted(n, l, 4242, dtype=np.float32)
+    rng = np.random.default_rng(4243)
+    perms = np.stack([rng.permutation(l) for _ in range(P)]).astype(np.int32)
+    x = torch.from_numpy(X).to(dev)
+    pt = torch.from_numpy(perms).to(dev)
+    ps = (n * (n - 1) // 2) * l * (P + 1)
+    out = {}
+    for mode, peak, mfmas in (("split", PEAK["bf16"], 3), ("fp32", PEAK["fp32"], 1)):
+        z, zd = pcc.normalize(x, mode)
+        c = torch.empty(n * (n - 1) // 2, dtype=torch.int32, device=dev)
+        ws = torch.empty(pcc.workspace_size(zd, 2), dtype=torch.uint8, device=dev)
+        pcc.permtest(z, zd, pt, out=c, workspace=ws)    # rows checked once, outside the timing
+        ms, _ = timed(lambda: pcc.permtest(z, zd, pt, out=c, validate=False, workspace=ws), 2,
+                      stream)
+        key = "permtest_long_split" if mode == "split" else "permtest_long_fp32"
+        out[key] = {"workload": f"n={n} l={l} P={P} {'split-BF16x3' if mode == 'split' else 'FP32'}"
+                                f" MFMA, tiled form (gather + tiles per group of permutations)",
+                    "ms": ms, "pair_samples_per_s": ps / (ms * 1e-3),
+                    "mfma_frac": 2.0 * mfmas * ps / (ms * 1e-3) / peak,
+                    "workspace_bytes": int(ws.numel())}
+        del z, ws
     return out
 
 

@@ -170,14 +170,22 @@ pcc_status pcc_normalize(const void *x, pcc_in_t xt, int64_t ldx,
                          const pcc_zdesc *zd, void *z, double *stats,
                          int32_t *n_degenerate, void *stream);
 
-/* Bytes of device workspace an operation needs.  op: 0 allpairs, 1 edges,
- * 2 permtest.  It is 0 for every op and layout: the tile kernels keep their
- * staging in LDS and registers, the edge counter is the caller's `count`,
- * and the permutation counts accumulate in LDS.  The `workspace` arguments
- * of those calls are therefore unused and may be NULL; they remain so that
- * a future kernel needing scratch does not change the ABI.  (The uneven
- * batch sizes its workspace with pcc_batch_workspace_size, the multi-pass
- * call its buffers with pcc_stream_buffer_bytes.) */
+/* Bytes of device workspace an operation needs (0 for an invalid layout).
+ * op 0 (pcc_allpairs), 1 (pcc_threshold_edges): 0 for every layout; the
+ *   tile kernels keep their staging in LDS and registers and the edge
+ *   counter is the caller's `count`, so their `workspace` arguments are
+ *   unused and may be NULL (kept so that a future kernel needing scratch
+ *   does not change the ABI).
+ * op 2 (pcc_permtest): 0 while l_pad <= pcc_permtest_max_l(mode) (the LDS
+ *   kernel, counts accumulate in LDS); for longer rows the size op 3 gives,
+ *   since the call then runs the tiled form.
+ * op 3 (pcc_permtest_tiles, FP32 and split layouts): the observed r
+ *   (n(n-1)/2 floats), S column-permuted copies of Z (S * zd->bytes) and,
+ *   when S > 1, S slots of int32 counts, S = min(32, max(1, 2^27 /
+ *   (n(n-1)/2))); each part 256-byte aligned.  Independent of P and of the
+ *   tile schedule.
+ * (The uneven batch sizes its workspace with pcc_batch_workspace_size, the
+ * multi-pass call its buffers with pcc_stream_buffer_bytes.) */
 size_t pcc_workspace_size(const pcc_zdesc *zd, int32_t op);
 
 /* All pairs (Sec. III-C, the tiled multithreaded kernel): tile jobs placed
@@ -271,30 +279,55 @@ pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
 
 /* Permutation test: the significance test by random permutations that the
  * evaluation (Sec. IV-A) motivates, at least 1,000 iterations of all-pairs
- * r on permuted data, in one persistent launch for all P permutations.
+ * r on permuted data.
  * For every pair y < x (r by Eq. (5)):
  *   r_obs = Z_y . Z_x,  r_p = sum_k Z_y[k] Z_x[perm_p[k]],
  *   counts[J'] = #{p : |r_p| >= |r_obs|}  (ties counted; -1 if r_obs is NaN)
  * The second operand (column x) is permuted; Z's mean and norm are
- * invariant under a permutation, so Z is not renormalised.  Jobs are 32 x 32
- * pair blocks whose two profile panels stay in LDS for all P permutations.
+ * invariant under a permutation, so Z is not renormalised.
+ * Rows of l_pad <= pcc_permtest_max_l(mode): one persistent launch for all
+ * P permutations; jobs are 32 x 32 pair blocks whose two profile panels
+ * stay in LDS for all P permutations; `workspace` is unused (may be NULL).
+ * Longer rows: the tiled form of pcc_permtest_tiles with the default
+ * schedule; `workspace` must hold pcc_workspace_size(zd, 2) bytes (NULL
+ * gives PCC_E_WORKSPACE).
  *   perms  device int32, P rows of l entries, each a permutation of 0..l-1.
  *          Not checked on the device: an entry outside [0, l) reads other
- *          LDS contents of the job (never outside the workgroup's LDS), so
- *          its counts are meaningless.  The Python binding checks them.
+ *          data of the job (LDS of the workgroup, or the row of Z in the
+ *          tiled form), so its counts are meaningless.  The Python binding
+ *          checks them.
  *   counts device int32, n(n-1)/2.
  * Supported modes: FP32 (FP32 MFMA; every r within about 1e-7 of exact) and
  * split-BF16x3 (three BF16 products per sample, about 2.7x the FP32 kernel's
  * rate; r within split's 1e-5, so a count can differ from the exact one only
  * in permutations whose |r| lies that close to |r_obs|).  The plain 16-bit
  * modes are refused: their r error (1e-4 and more) would decide too many
- * counts.  l_pad <= pcc_permtest_max_l(mode). */
+ * counts. */
 pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
                         const int32_t *perms, int32_t P, int32_t *counts,
                         void *workspace, void *stream);
 
-/* Largest l_pad pcc_permtest accepts (both 32-profile panels stay in LDS);
- * 0 for modes it does not support. */
+/* The permutation test on the all-pairs tiles, for rows of any length
+ * (Sec. IV-A's test on profiles of thousands of samples, as in the
+ * evaluation's data sets).  The observed r is computed first by the
+ * all-pairs tile kernel on schedule cfg (NULL: the default) into the
+ * workspace.  Then, per group of S permutations, S column-permuted copies
+ * of Z are gathered into the workspace and one launch runs the tiles of the
+ * upper triangle of Z against every copy with the same tile core, adding
+ * |r_p| >= |r_obs| to that copy's count slot; the slots are summed at the
+ * end.  An identity permutation reproduces r_obs bit for bit, so it counts.
+ * counts as for pcc_permtest; the r of a pair is the all-pairs kernel's on
+ * this schedule (the LDS kernel rounds in another order, so counts of the
+ * two forms can differ where some |r_p| lies within rounding of |r_obs|).
+ * workspace: device, workspace_bytes >= pcc_workspace_size(zd, 3), else
+ * PCC_E_WORKSPACE.  Modes as pcc_permtest. */
+pcc_status pcc_permtest_tiles(const pcc_zdesc *zd, const void *z, const int32_t *perms,
+                              int32_t P, int32_t *counts, const pcc_tile_cfg *cfg,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Largest l_pad of the LDS form of pcc_permtest (both 32-profile panels
+ * stay in LDS); longer rows take the tiled form.  0 for modes the
+ * permutation test does not support. */
 int64_t pcc_permtest_max_l(pcc_mode_t mode);
 
 /* ---- Uneven batches -----------------------------------------------------

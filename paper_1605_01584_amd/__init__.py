@@ -107,6 +107,7 @@ _sig("pcc_threshold_edges_xy", _i32, _zdp, _vp, _zdp, _vp, _f32, _vp, _vp, _i64,
 _sig("pcc_edges_status", _i32, _i64, _i64)
 _sig("pcc_permtest", _i32, _zdp, _vp, _vp, _i32, _vp, _vp, _vp)
 _sig("pcc_permtest_max_l", _i64, _i32)
+_sig("pcc_permtest_tiles", _i32, _zdp, _vp, _vp, _i32, _vp, _cfgp, _vp, ctypes.c_size_t, _vp)
 _sig("pcc_batch_workspace_size", ctypes.c_size_t, _i32)
 _sig("pcc_batch_plan_create", _i32, _i32, ctypes.POINTER(BatchItem), _i32, _vp, ctypes.c_size_t,
      _vp, ctypes.POINTER(_vp))
@@ -138,6 +139,7 @@ EXPORTED = [
     "pcc_cell_of_job", "pcc_packed_index", "pcc_packed_cell", "pcc_cells_host",
     "pcc_tile_order_host", "pcc_cells_device", "pcc_autotune", "pcc_device_cus",
     "pcc_autotune_default_count", "pcc_tile_arith", "pcc_batch_run_noalloc",
+    "pcc_permtest_tiles",
 ]
 
 BATCH_NOALLOC_MAX_D = 256  # PCC_BATCH_NOALLOC_MAX_D
@@ -424,10 +426,12 @@ def threshold_edges(z, zd: ZDesc, thr: float, cap: int, cfg: Optional[TileCfg] =
     return ij[:c], rv[:c], c
 
 
-def permtest(z, zd: ZDesc, perms, out=None, stream=None, validate: bool = True):
-    """Counts of |r_perm| >= |r_obs| over the P rows of perms (device int32 P x l).
-    z in the "fp32" or "split" layout (the arithmetic follows the layout).
-    validate=True checks on the device that every row is a permutation."""
+def workspace_size(zd: ZDesc, op: int) -> int:
+    """pcc_workspace_size: 0 allpairs, 1 edges, 2 permtest, 3 permtest_tiles."""
+    return _lib.pcc_workspace_size(ctypes.byref(zd), int(op))
+
+
+def _perm_args(zd: ZDesc, perms, validate: bool):
     torch = _torch()
     if perms.dtype != torch.int32 or perms.dim() != 2 or perms.shape[1] != zd.l:
         raise ValueError("perms must be int32 (P, l)")
@@ -437,12 +441,53 @@ def permtest(z, zd: ZDesc, perms, out=None, stream=None, validate: bool = True):
         srt = torch.sort(perms, dim=1).values
         if not bool((srt == torch.arange(zd.l, device=perms.device, dtype=torch.int32)).all()):
             raise ValueError("every row of perms must be a permutation of 0..l-1")
+    return perms
+
+
+def _counts_out(torch, zd: ZDesc, out, device):
     npairs = zd.n * (zd.n - 1) // 2
     if out is None:
-        out = torch.empty(npairs, dtype=torch.int32, device=z.device)
+        return torch.empty(npairs, dtype=torch.int32, device=device)
+    if out.numel() < npairs or out.dtype != torch.int32:
+        raise ValueError("out must hold n(n-1)/2 int32")
+    return out
+
+
+def permtest(z, zd: ZDesc, perms, out=None, stream=None, validate: bool = True, workspace=None):
+    """Counts of |r_perm| >= |r_obs| over the P rows of perms (device int32 P x l).
+    z in the "fp32" or "split" layout (the arithmetic follows the layout).
+    Rows longer than permtest_max_l take the tiled form, with a workspace of
+    workspace_size(zd, 2) bytes (allocated here unless given).
+    validate=True checks on the device that every row is a permutation."""
+    torch = _torch()
+    perms = _perm_args(zd, perms, validate)
+    out = _counts_out(torch, zd, out, z.device)
+    ws = workspace_size(zd, 2)
+    if ws and workspace is None:
+        workspace = torch.empty(ws, dtype=torch.uint8, device=z.device)
     _check(_lib.pcc_permtest(ctypes.byref(zd), _dev_ptr(z, "z"), _dev_ptr(perms, "perms"),
-                             perms.shape[0], _dev_ptr(out, "counts"), None,
+                             perms.shape[0], _dev_ptr(out, "counts"),
+                             _dev_ptr(workspace, "workspace") if ws else None,
                              _stream(torch, stream)), "pcc_permtest")
+    return out
+
+
+def permtest_tiles(z, zd: ZDesc, perms, cfg: Optional[TileCfg] = None, out=None, stream=None,
+                   validate: bool = True, workspace=None):
+    """The tiled permutation test (any row length): as permtest, on the
+    all-pairs tile schedule cfg; workspace of workspace_size(zd, 3) bytes."""
+    torch = _torch()
+    perms = _perm_args(zd, perms, validate)
+    out = _counts_out(torch, zd, out, z.device)
+    ws = workspace_size(zd, 3)
+    if workspace is None:
+        workspace = torch.empty(max(ws, 1), dtype=torch.uint8, device=z.device)
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(_lib.pcc_permtest_tiles(ctypes.byref(zd), _dev_ptr(z, "z"), _dev_ptr(perms, "perms"),
+                                   perms.shape[0], _dev_ptr(out, "counts"),
+                                   ctypes.byref(cfg) if cfg is not None else None,
+                                   _dev_ptr(workspace, "workspace"), nbytes,
+                                   _stream(torch, stream)), "pcc_permtest_tiles")
     return out
 
 

@@ -34,6 +34,10 @@ int tile_occupancy(int mode, int tile, int epi);
 hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *perms, int32_t P,
                            int32_t *counts, int cus, hipStream_t st);
 int64_t permtest_max_l(int mode);
+size_t permtest_tiles_workspace(const pcc_zdesc &zd);
+hipError_t launch_permtest_tiles(const pcc_zdesc &zd, const void *z, const int32_t *perms,
+                                 int32_t P, int32_t *counts, void *ws, const pcc_tile_cfg &cfg,
+                                 int cus, hipStream_t st);
 
 namespace {
 
@@ -202,8 +206,11 @@ pcc_status pcc_normalize(const void *x, pcc_in_t xt, int64_t ldx, const pcc_zdes
 }
 
 size_t pcc_workspace_size(const pcc_zdesc *zd, int32_t op) {
-  (void)zd;
-  (void)op;
+  if (check_zdesc(zd) != PCC_OK || zd->n < 2) return 0;
+  const bool perm_mode = zd->mode == PCC_FP32 || zd->mode == PCC_SPLIT_BF16X3;
+  if (op == 2 && perm_mode && zd->l_pad > permtest_max_l(zd->mode))
+    return permtest_tiles_workspace(*zd);
+  if (op == 3 && perm_mode) return permtest_tiles_workspace(*zd);
   return 0;
 }
 
@@ -402,16 +409,38 @@ int64_t pcc_permtest_max_l(pcc_mode_t mode) { return permtest_max_l(mode); }
 
 pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z, const int32_t *perms, int32_t P,
                         int32_t *counts, void *workspace, void *stream) {
-  (void)workspace;
   pcc_status s = check_zdesc(zd);
   if (s != PCC_OK) return s;
   if (zd->n < 2) return PCC_E_SHAPE;  // no pair
   if (!z || !counts || P < 0 || (P > 0 && !perms)) return PCC_E_ARG;
   if (permtest_max_l(zd->mode) <= 0) return PCC_E_MODE;
-  if (zd->l_pad > permtest_max_l(zd->mode)) return PCC_E_SHAPE;
   const int cus = device_cus();
+  if (zd->l_pad > permtest_max_l(zd->mode)) {
+    // rows too long for the LDS kernel: the tiled form
+    if (!workspace) return PCC_E_WORKSPACE;
+    pcc_tile_cfg c;
+    pcc_default_cfg(zd, &c);
+    return hip_status(launch_permtest_tiles(*zd, z, perms, P, counts, workspace, c, cus,
+                                            (hipStream_t)stream));
+  }
   return hip_status(
       launch_permtest(*zd, z, perms, P, counts, cus > 0 ? cus : 256, (hipStream_t)stream));
+}
+
+pcc_status pcc_permtest_tiles(const pcc_zdesc *zd, const void *z, const int32_t *perms, int32_t P,
+                              int32_t *counts, const pcc_tile_cfg *cfg, void *workspace,
+                              size_t workspace_bytes, void *stream) {
+  pcc_status s = check_zdesc(zd);
+  if (s != PCC_OK) return s;
+  if (zd->n < 2) return PCC_E_SHAPE;
+  if (!z || !counts || P < 0 || (P > 0 && !perms)) return PCC_E_ARG;
+  if (zd->mode != PCC_FP32 && zd->mode != PCC_SPLIT_BF16X3) return PCC_E_MODE;
+  pcc_tile_cfg c;
+  s = check_cfg(*zd, cfg, c);
+  if (s != PCC_OK) return s;
+  if (!workspace || workspace_bytes < permtest_tiles_workspace(*zd)) return PCC_E_WORKSPACE;
+  return hip_status(launch_permtest_tiles(*zd, z, perms, P, counts, workspace, c, device_cus(),
+                                          (hipStream_t)stream));
 }
 
 int64_t pcc_job_of_cell(int64_t m, int64_t y, int64_t x) { return tri_F(m, y) + x - y; }

@@ -22,9 +22,19 @@
 // integers from |r| differences) and split-BF16x3 (three
 // v_mfma_f32_32x32x16_bf16 per 16 samples, about 2.7x the FP32 kernel's rate,
 // r within split's 1e-5).
+#include <algorithm>
+
 #include "pcc_internal.h"
 
 namespace pcc {
+hipError_t launch_allpairs(const pcc_zdesc &zd, const void *z, float *r, const pcc_tile_cfg &cfg,
+                           int grid, hipStream_t st);
+hipError_t launch_perm_tiles(const pcc_zdesc &zd, const void *z, const unsigned char *zp,
+                             int64_t zp_stride, const float *robs, int32_t *cnt,
+                             int64_t cnt_stride, int slots, const pcc_tile_cfg &cfg, int cus,
+                             hipStream_t st);
+int tile_occupancy(int mode, int tile, int epi);
+
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -373,6 +383,182 @@ int64_t max_lds_per_block() {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Permutation test on tiles, for rows of any length (the LDS kernel above
+// holds both panels for every sample, which caps l_pad).  Per group of S
+// permutations: S column-permuted copies of Z are gathered into the
+// workspace, then one tile launch runs the symmetric tile schedule of Z
+// against each copy (the all-pairs tile core, so an identity permutation
+// reproduces the observed r bit for bit) and adds |r_p| >= |r_obs| to the
+// copy's slot of counts; the slots are summed at the end.  The observed r
+// comes first, from the all-pairs kernel on the same schedule.
+
+// Row x of copy s: sample k of the copy is sample perms[p0 + s][k] of row x
+// of Z (k < l); padding samples stay zero.  FP32 rows are l_pad floats in
+// sample order; a split row is 128-byte chunks of 32 BF16 hi values and the
+// 32 matching lo values.  One workgroup per (row, copy); a thread writes one
+// 16-byte unit (FP32: 4 samples) or one hi unit and its lo unit (split: 8
+// samples).
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void perm_gather_kernel(const unsigned char *__restrict__ z,
+                                                         int64_t row_bytes, int64_t l,
+                                                         int64_t l_pad,
+                                                         const int32_t *__restrict__ perms,
+                                                         int64_t p0, unsigned char *__restrict__ zp,
+                                                         int64_t zp_stride) {
+  const int64_t x = blockIdx.x, s = blockIdx.y;
+  const unsigned char *src = z + x * row_bytes;
+  unsigned char *dst = zp + s * zp_stride + x * row_bytes;
+  const int32_t *pr = perms + (p0 + s) * l;
+  if constexpr (SPLIT) {
+    const int64_t units = l_pad / 8;  // groups of 8 samples
+    for (int64_t q = threadIdx.x; q < units; q += blockDim.x) {
+      const int64_t c = q >> 2, u = q & 3, k0 = 8 * q;
+      uint32_t hw[4], lw[4];
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        uint32_t hv[2], lv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t k = k0 + 2 * e2 + h;
+          hv[h] = lv[h] = 0u;
+          if (k < l) {
+            const int64_t pk = pr[k];
+            const unsigned char *sp = src + (pk >> 5) * 128 + (pk & 31) * 2;
+            hv[h] = *reinterpret_cast<const uint16_t *>(sp);
+            lv[h] = *reinterpret_cast<const uint16_t *>(sp + 64);
+          }
+        }
+        hw[e2] = hv[0] | (hv[1] << 16);
+        lw[e2] = lv[0] | (lv[1] << 16);
+      }
+      unsigned char *d = dst + c * 128 + 16 * u;
+      *reinterpret_cast<u32x4 *>(d) = u32x4{hw[0], hw[1], hw[2], hw[3]};
+      *reinterpret_cast<u32x4 *>(d + 64) = u32x4{lw[0], lw[1], lw[2], lw[3]};
+    }
+  } else {
+    const int64_t units = l_pad / 4;
+    const float *sf = reinterpret_cast<const float *>(src);
+    for (int64_t q = threadIdx.x; q < units; q += blockDim.x) {
+      f32x4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t k = 4 * q + e;
+        v[e] = k < l ? sf[pr[k]] : 0.0f;
+      }
+      *reinterpret_cast<f32x4 *>(dst + 16 * q) = v;
+    }
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t count, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// counts[J] = -1 where the observed r is NaN (a degenerate profile), else the
+// sum of the slots' counts (slots == 0: counts already holds them).
+__global__ void perm_finalize_kernel(int32_t *__restrict__ counts, const float *__restrict__ robs,
+                                     const int32_t *__restrict__ slot0, int slots, int64_t stride,
+                                     int64_t np) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float ro = robs[i];
+    int32_t c = 0;
+    if (slots == 0) {
+      c = counts[i];
+    } else {
+      for (int s = 0; s < slots; ++s) c += slot0[s * stride + i];
+    }
+    counts[i] = (ro == ro) ? c : -1;
+  }
+}
+
+// Copies of Z (and count slots) per launch of the tiled permutation test:
+// enough tile jobs per launch to fill the grid for a few rounds (about 2^27
+// pair-copies), at most 32.
+int permtest_slots(int64_t npairs) {
+  if (npairs <= 0) return 1;
+  int64_t s = ((int64_t)1 << 27) / npairs;
+  if (s < 1) s = 1;
+  if (s > 32) s = 32;
+  return (int)s;
+}
+
+// Workspace of the tiled permutation test: [observed r | count slots (when
+// more than one) | permuted copies of Z], each part 256-byte aligned.
+struct PermWs {
+  float *robs;
+  int32_t *slots;
+  int64_t slot_stride;  // counts between slots
+  unsigned char *zp;
+  size_t bytes;
+};
+
+PermWs perm_ws(const pcc_zdesc &zd, void *base) {
+  const int64_t np = zd.n * (zd.n - 1) / 2;
+  const int S = permtest_slots(np);
+  const size_t rb = ((size_t)np * 4 + 255) / 256 * 256;
+  unsigned char *b = (unsigned char *)base;
+  PermWs w;
+  w.robs = (float *)b;
+  w.slots = S > 1 ? (int32_t *)(b + rb) : nullptr;
+  w.slot_stride = (int64_t)(rb / 4);
+  const size_t sb = S > 1 ? (size_t)S * rb : 0;
+  w.zp = b + rb + sb;
+  w.bytes = rb + sb + (size_t)S * (size_t)zd.bytes;
+  return w;
+}
+
+size_t permtest_tiles_workspace(const pcc_zdesc &zd) { return perm_ws(zd, nullptr).bytes; }
+
+hipError_t launch_permtest_tiles(const pcc_zdesc &zd, const void *z, const int32_t *perms,
+                                 int32_t P, int32_t *counts, void *ws, const pcc_tile_cfg &cfg,
+                                 int cus, hipStream_t st) {
+  const int64_t np = zd.n * (zd.n - 1) / 2;
+  const int S = permtest_slots(np);
+  const PermWs w = perm_ws(zd, ws);
+  const int amode = arith_mode(zd);
+  int occ = tile_occupancy(amode, cfg.tile, 0);
+  if (occ < 1) occ = 1;
+  const int64_t m = (zd.n + cfg.tile - 1) / cfg.tile;
+  int64_t grid = cfg.grid > 0 ? cfg.grid : (int64_t)(cus > 0 ? cus : 256) * occ;
+  if (grid > m * (m + 1) / 2) grid = m * (m + 1) / 2;
+  hipError_t e = launch_allpairs(zd, z, w.robs, cfg, (int)grid, st);
+  if (e != hipSuccess) return e;
+  int32_t *cnt0 = S > 1 ? w.slots : counts;
+  const int64_t cnt_stride = S > 1 ? w.slot_stride : 0;
+  const int64_t nfill = S > 1 ? (int64_t)S * w.slot_stride : np;
+  const int fblocks = (int)std::min<int64_t>((nfill + 255) / 256, 4096);
+  if (nfill > 0) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(fblocks), dim3(256), 0, st, cnt0, nfill, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const bool split = amode == PCC_SPLIT_BF16X3;
+  for (int64_t p0 = 0; p0 < P; p0 += S) {
+    const int sc = (int)std::min<int64_t>(S, P - p0);
+    if (split)
+      hipLaunchKernelGGL(perm_gather_kernel<true>, dim3((unsigned)zd.n_pad, (unsigned)sc), dim3(256),
+                         0, st, (const unsigned char *)z, zd.row_bytes, zd.l, zd.l_pad, perms, p0,
+                         w.zp, zd.bytes);
+    else
+      hipLaunchKernelGGL(perm_gather_kernel<false>, dim3((unsigned)zd.n_pad, (unsigned)sc),
+                         dim3(256), 0, st, (const unsigned char *)z, zd.row_bytes, zd.l, zd.l_pad,
+                         perms, p0, w.zp, zd.bytes);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_perm_tiles(zd, z, w.zp, zd.bytes, w.robs, cnt0, cnt_stride, sc, cfg, cus, st);
+    if (e != hipSuccess) return e;
+  }
+  const int nblocks = (int)std::min<int64_t>((np + 255) / 256, 4096);
+  if (np > 0) {
+    hipLaunchKernelGGL(perm_finalize_kernel, dim3(nblocks), dim3(256), 0, st, counts, w.robs,
+                       cnt0, S > 1 ? S : 0, cnt_stride, np);
+    e = hipGetLastError();
+  }
+  return e;
+}
 
 int64_t permtest_max_l(int mode) {
   if (mode != PCC_FP32 && mode != PCC_SPLIT_BF16X3) return 0;

@@ -59,7 +59,11 @@ typedef __attribute__((address_space(3))) void lds_void;
 //   EPI_RECT        non-symmetric, r[y * ldr + x], FP32
 //   EPI_RECT_EDGES  non-symmetric edge list
 //   EPI_PACKED_F64  symmetric, packed, FP64 r (FP64 mode only)
-enum { EPI_PACKED = 0, EPI_EDGES = 1, EPI_RECT = 2, EPI_RECT_EDGES = 3, EPI_PACKED_F64 = 4 };
+//   EPI_PERM        symmetric job matrix of Z against a column-permuted copy
+//                   of Z: cnt[J'] += 1 where |r| >= |robs[J']| (permutation
+//                   test; the job owning a tile is its only writer)
+enum { EPI_PACKED = 0, EPI_EDGES = 1, EPI_RECT = 2, EPI_RECT_EDGES = 3, EPI_PACKED_F64 = 4,
+       EPI_PERM = 5 };
 
 constexpr int kTileThreads = 512;  // 8 waves
 // num_records of the panel buffer descriptors: 2^32 - 1 bytes.  A panel is at
@@ -90,6 +94,8 @@ struct EpiArgs {
   float *rv;
   int64_t cap;
   unsigned long long *count;
+  const float *robs;        // permutation test: observed r, packed
+  int32_t *cnt;             // permutation test: counts, packed
 };
 
 template <int TILE> struct TileShape {
@@ -138,6 +144,10 @@ template <int EPI> struct Epi {
                                               T rv) {
     if constexpr (EPI == EPI_PACKED_F64) {
       ea.r64[rb + x] = (double)rv;
+    } else if constexpr (EPI == EPI_PERM) {
+      // NaN on either side never counts (the caller marks such pairs)
+      const float ro = ea.robs[rb + x];
+      if ((rv < (T)0 ? -rv : rv) >= (T)(ro < 0.0f ? -ro : ro)) ea.cnt[rb + x] += 1;
     } else if constexpr (kEdges) {
       if ((rv < (T)0 ? -rv : rv) >= (T)ea.thr) {
         const unsigned long long s = atomicAdd(ea.count, 1ull);

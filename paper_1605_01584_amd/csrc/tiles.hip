@@ -78,6 +78,49 @@ __global__ __launch_bounds__(kTileThreads, 1) void tile_kernel(UniformArgs a) {
 
 __global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
 
+// Permutation test on tiles: slot s of a launch holds one column-permuted
+// copy of Z (at zp + s * zp_stride) and its own counts (cnt + s *
+// cnt_stride).  A job is (slot, tile), the tiles of a slot numbered as the
+// symmetric schedule numbers them; every job is the only writer of its
+// slot's counts in its tile.
+struct PermTileArgs {
+  ZView zv;                  // zc is set per job
+  EpiArgs ea;                // robs, cnt (slot 0)
+  const unsigned char *zp;
+  int64_t zp_stride;         // bytes
+  int64_t cnt_stride;        // counts
+  int64_t m;                 // tiles per side
+  int64_t T;                 // tiles per slot: m(m+1)/2
+  int64_t njobs;             // slots * T
+  int32_t order;
+  int32_t band;
+};
+
+template <int MODE, int TILE>
+__global__ __launch_bounds__(kTileThreads, 1) void perm_tile_kernel(PermTileArgs a) {
+  __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
+  const int64_t G = gridDim.x;
+  for (int64_t u = xcd_slot(blockIdx.x, G); u < a.njobs; u += G) {
+    const int64_t s = u / a.T, t = u - s * a.T;
+    const Cell tc = tile_of_job(a.m, a.order, a.band, t);
+    ZView zv = a.zv;
+    zv.zc = a.zp + s * a.zp_stride;
+    EpiArgs ea = a.ea;
+    ea.cnt = a.ea.cnt + s * a.cnt_stride;
+    do_tile<MODE, TILE, EPI_PERM>(zv, ea, tc.y, tc.x, smem);
+  }
+}
+
+const void *perm_kernel_for(int mode, int tile) {
+  if (mode == PCC_FP32)
+    return tile == 128 ? (const void *)perm_tile_kernel<PCC_FP32, 128>
+                       : (const void *)perm_tile_kernel<PCC_FP32, 256>;
+  if (mode == PCC_SPLIT_BF16X3)
+    return tile == 128 ? (const void *)perm_tile_kernel<PCC_SPLIT_BF16X3, 128>
+                       : (const void *)perm_tile_kernel<PCC_SPLIT_BF16X3, 256>;
+  return nullptr;
+}
+
 template <int MODE, int EPI> const void *kernel_ptr_t(int tile) {
   if constexpr (MODE == PCC_FP64)
     return tile == 128 ? (const void *)tile_kernel<MODE, 128, EPI> : nullptr;
@@ -262,6 +305,44 @@ hipError_t launch_edges_xy(const pcc_zdesc &zdx, const void *zx, const pcc_zdesc
   a.ea.cap = cap;
   a.ea.count = (unsigned long long *)count;
   return launch(arith_mode(zdx), a, cfg.tile, EPI_RECT_EDGES, grid, st);
+}
+
+// One launch of the tiled permutation test: `slots` permuted copies of Z
+// against Z over the symmetric tile schedule of cfg, counts added in place.
+hipError_t launch_perm_tiles(const pcc_zdesc &zd, const void *z, const unsigned char *zp,
+                             int64_t zp_stride, const float *robs, int32_t *cnt,
+                             int64_t cnt_stride, int slots, const pcc_tile_cfg &cfg, int cus,
+                             hipStream_t st) {
+  const int mode = arith_mode(zd);
+  const void *k = perm_kernel_for(mode, cfg.tile);
+  if (!k) return hipErrorInvalidValue;
+  UniformArgs u = make_args(zd, z, cfg);
+  PermTileArgs a{};
+  a.zv = u.zv;
+  a.ea.robs = robs;
+  a.ea.cnt = cnt;
+  a.zp = zp;
+  a.zp_stride = zp_stride;
+  a.cnt_stride = cnt_stride;
+  a.m = u.mr;
+  a.T = u.njobs;
+  a.njobs = (int64_t)slots * u.njobs;
+  a.order = cfg.order;
+  a.band = cfg.band;
+  if (a.njobs <= 0) return hipSuccess;
+  static std::atomic<int> occ_cache[2][2] = {};
+  std::atomic<int> &oc = occ_cache[mode == PCC_FP32 ? 0 : 1][cfg.tile == 128 ? 0 : 1];
+  int occ = oc.load(std::memory_order_relaxed);
+  if (occ == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kTileThreads, 0) != hipSuccess ||
+        occ < 1)
+      occ = 1;
+    oc.store(occ, std::memory_order_relaxed);
+  }
+  int64_t grid = cfg.grid > 0 ? cfg.grid : (int64_t)(cus > 0 ? cus : 256) * occ;
+  if (grid > a.njobs) grid = a.njobs;
+  void *args[] = {(void *)&a};
+  return hipLaunchKernel(k, dim3((unsigned)grid), dim3(kTileThreads), args, 0, st);
 }
 
 hipError_t launch_cells(int64_t m, int diag, int64_t J0, int64_t count, int64_t *y, int64_t *x,

@@ -111,8 +111,22 @@ def test_host_argument_errors_return_before_launch():
     # permtest: unsupported mode, too long rows, null perms with P > 0
     zs = pcc.z_layout(100, 50, "bf16")
     assert lib.pcc_permtest(ctypes.byref(zs), fake, fake, 3, fake, None, None) == pcc.PCC_E_MODE
+    # rows past the LDS form take the tiled form, which needs a workspace
     zl = pcc.z_layout(100, 100000, "fp32")
-    assert lib.pcc_permtest(ctypes.byref(zl), fake, fake, 3, fake, None, None) == pcc.PCC_E_SHAPE
+    assert lib.pcc_permtest(ctypes.byref(zl), fake, fake, 3, fake, None, None) == pcc.PCC_E_WORKSPACE
+    # tiled form: mode, workspace, schedule
+    need = lib.pcc_workspace_size(ctypes.byref(zl), 3)
+    assert lib.pcc_permtest_tiles(ctypes.byref(zs), fake, fake, 3, fake, None, fake, 1 << 40,
+                                  None) == pcc.PCC_E_MODE
+    assert lib.pcc_permtest_tiles(ctypes.byref(zl), fake, fake, 3, fake, None, fake, need - 1,
+                                  None) == pcc.PCC_E_WORKSPACE
+    assert lib.pcc_permtest_tiles(ctypes.byref(zl), fake, fake, 3, fake, None, None, need,
+                                  None) == pcc.PCC_E_WORKSPACE
+    bad = pcc.TileCfg(64, 0, 1, 0)
+    assert lib.pcc_permtest_tiles(ctypes.byref(zl), fake, fake, 3, fake, ctypes.byref(bad), fake,
+                                  need, None) == pcc.PCC_E_ARG
+    assert lib.pcc_permtest_tiles(ctypes.byref(zl), fake, None, 3, fake, None, fake, need,
+                                  None) == pcc.PCC_E_ARG
     assert lib.pcc_permtest(ctypes.byref(zd), fake, None, 3, fake, None, None) == pcc.PCC_E_ARG
     assert lib.pcc_permtest(ctypes.byref(zd), fake, fake, -1, fake, None, None) == pcc.PCC_E_ARG
     # batch plan: bad counts / missing workspace
@@ -135,11 +149,29 @@ def test_host_argument_errors_return_before_launch():
     assert lib.pcc_cells_device(10, 1, 0, 5, None, fake, None) == pcc.PCC_E_ARG
 
 
+def _perm_ws(n, l, mode):
+    """The tiled permutation test's workspace, from its definition: observed r,
+    S count slots when S > 1, S copies of Z; 256-byte aligned parts."""
+    import paper_1605_01584_amd as pcc
+    zd = pcc.z_layout(n, l, mode)
+    np_ = n * (n - 1) // 2
+    S = min(32, max(1, (1 << 27) // np_))
+    rb = (np_ * 4 + 255) // 256 * 256
+    return rb + (S * rb if S > 1 else 0) + S * zd.bytes
+
+
 def test_workspace_sizes():
     import paper_1605_01584_amd as pcc
     zd = pcc.z_layout(1000, 100, "split")
     for op in range(3):
         assert pcc._lib.pcc_workspace_size(ctypes.byref(zd), op) == 0
+    for n, l, mode in [(1000, 100, "split"), (600, 5000, "fp32"), (4096, 5000, "split"),
+                       (32768, 4096, "split"), (2, 700, "fp32")]:
+        zd = pcc.z_layout(n, l, mode)
+        assert pcc.workspace_size(zd, 3) == _perm_ws(n, l, mode)
+        long_rows = zd.l_pad > pcc.permtest_max_l(mode)
+        assert pcc.workspace_size(zd, 2) == (_perm_ws(n, l, mode) if long_rows else 0)
+    assert pcc.workspace_size(pcc.z_layout(600, 5000, "bf16"), 2) == 0
     assert pcc._lib.pcc_batch_workspace_size(64) >= 256 + 64 * 64
     assert pcc._lib.pcc_batch_workspace_size(64) % 256 == 0
 

@@ -70,21 +70,19 @@ def test_small_all_pairs(mode, n, l, P):
 @pytest.mark.parametrize("mode", ["fp32", "split"])
 def test_longest_rows(mode):
     """Rows of the longest length the LDS holds (both 32-profile panels and
-    the count block fill the workgroup's LDS), and one sample past it refused."""
-    import torch
+    the count block fill the workgroup's LDS), and rows one sample past it,
+    which take the tiled form, both against the oracle."""
     import paper_1605_01584_amd as pcc
     lmax = pcc.permtest_max_l(mode)
     rng = np.random.default_rng(lmax)
     n, P = 70, 9
-    X, _ = workloads.planted(n, lmax, 11, n_planted=3, dtype=np.float32)
-    perms = np.stack([rng.permutation(lmax) for _ in range(P)]).astype(np.int32)
-    got = _gpu_counts(X, perms, mode)
-    I, J = np.triu_indices(n, 1)
-    _check(got, X, perms, I, J, mode)
-    z, zd = pcc.normalize(to_device(rng.standard_normal((n, lmax + 1)).astype(np.float32)), mode)
-    with pytest.raises(pcc.PccError):
-        pcc.permtest(z, zd, torch.from_numpy(perms[:, :1].repeat(lmax + 1, 1) * 0).cuda(),
-                     validate=False)
+    for l in (lmax, lmax + 1):
+        X, _ = workloads.planted(n, l, 11, n_planted=3, dtype=np.float32)
+        perms = np.stack([rng.permutation(l) for _ in range(P)]).astype(np.int32)
+        assert (pcc.workspace_size(pcc.z_layout(n, l, mode), 2) > 0) == (l > lmax)
+        got = _gpu_counts(X, perms, mode)
+        I, J = np.triu_indices(n, 1)
+        _check(got, X, perms, I, J, mode)
 
 
 @pytest.mark.parametrize("mode", ["fp32", "split"])
