@@ -310,7 +310,8 @@ pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
 /* The permutation test on the all-pairs tiles, for rows of any length
  * (Sec. IV-A's test on profiles of thousands of samples, as in the
  * evaluation's data sets).  The observed r is computed first by the
- * all-pairs tile kernel on schedule cfg (NULL: the default) into the
+ * all-pairs tile kernel on schedule cfg (NULL: the all-pairs default, with
+ * 256-wide tiles when the S copies of a launch fill the grid with them) into the
  * workspace.  Then, per group of S permutations, S column-permuted copies
  * of Z are gathered into the workspace and one launch runs the tiles of the
  * upper triangle of Z against every copy with the same tile core, adding

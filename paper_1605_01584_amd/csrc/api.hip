@@ -35,6 +35,7 @@ hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *pe
                            int32_t *counts, int cus, hipStream_t st);
 int64_t permtest_max_l(int mode);
 size_t permtest_tiles_workspace(const pcc_zdesc &zd);
+int permtest_slots(int64_t npairs);
 hipError_t launch_permtest_tiles(const pcc_zdesc &zd, const void *z, const int32_t *perms,
                                  int32_t P, int32_t *counts, void *ws, const pcc_tile_cfg &cfg,
                                  int cus, hipStream_t st);
@@ -407,6 +408,22 @@ pcc_status pcc_edges_status(int64_t count_host, int64_t cap) {
 
 int64_t pcc_permtest_max_l(pcc_mode_t mode) { return permtest_max_l(mode); }
 
+// Default schedule of the tiled permutation test: the all-pairs default,
+// with 256-wide tiles whenever the copies of one launch give the grid a few
+// rounds of them (one launch holds S copies' tiles).
+static pcc_tile_cfg perm_default_cfg(const pcc_zdesc &zd) {
+  pcc_tile_cfg c;
+  pcc_default_cfg(&zd, &c);
+  const int64_t S = permtest_slots(zd.n * (zd.n - 1) / 2);
+  const int64_t m = (zd.n + 255) / 256;
+  if (c.tile == 128 && S * (m * (m + 1) / 2) >= 4 * 256) {
+    c.tile = 256;
+    c.order = 1;
+    c.band = 8;
+  }
+  return c;
+}
+
 pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z, const int32_t *perms, int32_t P,
                         int32_t *counts, void *workspace, void *stream) {
   pcc_status s = check_zdesc(zd);
@@ -418,8 +435,7 @@ pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z, const int32_t *perms
   if (zd->l_pad > permtest_max_l(zd->mode)) {
     // rows too long for the LDS kernel: the tiled form
     if (!workspace) return PCC_E_WORKSPACE;
-    pcc_tile_cfg c;
-    pcc_default_cfg(zd, &c);
+    const pcc_tile_cfg c = perm_default_cfg(*zd);
     return hip_status(launch_permtest_tiles(*zd, z, perms, P, counts, workspace, c, cus,
                                             (hipStream_t)stream));
   }
@@ -435,9 +451,11 @@ pcc_status pcc_permtest_tiles(const pcc_zdesc *zd, const void *z, const int32_t 
   if (zd->n < 2) return PCC_E_SHAPE;
   if (!z || !counts || P < 0 || (P > 0 && !perms)) return PCC_E_ARG;
   if (zd->mode != PCC_FP32 && zd->mode != PCC_SPLIT_BF16X3) return PCC_E_MODE;
-  pcc_tile_cfg c;
-  s = check_cfg(*zd, cfg, c);
-  if (s != PCC_OK) return s;
+  pcc_tile_cfg c = perm_default_cfg(*zd);
+  if (cfg) {
+    s = check_cfg(*zd, cfg, c);
+    if (s != PCC_OK) return s;
+  }
   if (!workspace || workspace_bytes < permtest_tiles_workspace(*zd)) return PCC_E_WORKSPACE;
   return hip_status(launch_permtest_tiles(*zd, z, perms, P, counts, workspace, c, device_cus(),
                                           (hipStream_t)stream));

@@ -397,9 +397,79 @@ int64_t max_lds_per_block() {
 // Row x of copy s: sample k of the copy is sample perms[p0 + s][k] of row x
 // of Z (k < l); padding samples stay zero.  FP32 rows are l_pad floats in
 // sample order; a split row is 128-byte chunks of 32 BF16 hi values and the
-// 32 matching lo values.  One workgroup per (row, copy); a thread writes one
-// 16-byte unit (FP32: 4 samples) or one hi unit and its lo unit (split: 8
-// samples).
+// 32 matching lo values.
+//
+// A workgroup takes R rows and every copy of the launch.  The R rows are
+// first staged in LDS as one 32-bit word per sample (the FP32 value, or the
+// sample's hi in the low half and lo in the high half), so every gathered
+// sample is one LDS read and each row is read from memory once per launch;
+// each index of a permutation serves R rows.  A thread then writes 16-byte
+// units of the copies: 4 samples (FP32), or the hi unit and lo unit of 8
+// samples (split).
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void perm_gather_lds_kernel(
+    const unsigned char *__restrict__ z, int64_t row_bytes, int64_t n_pad, int64_t l,
+    int64_t l_pad, int R, const int32_t *__restrict__ perms, int64_t p0, int copies,
+    unsigned char *__restrict__ zp, int64_t zp_stride) {
+  extern __shared__ __align__(16) uint32_t rows[];  // R x l_pad words
+  const int64_t x0 = (int64_t)blockIdx.x * R;
+  const int nr = (int)((n_pad - x0) < R ? (n_pad - x0) : R);
+  const int64_t u4 = l_pad / 4;  // 16-byte units of a staged row
+  for (int64_t q = threadIdx.x; q < (int64_t)nr * u4; q += blockDim.x) {
+    const int64_t r = q / u4, u = q - r * u4;
+    u32x4 v;
+    if constexpr (SPLIT) {
+      // samples 4u .. 4u + 3: hi at chunk c, position 4u % 32, lo 64 bytes on
+      const int64_t k = 4 * u, c = k >> 5, o = k & 31;
+      const unsigned char *src = z + (x0 + r) * row_bytes + c * 128 + 2 * o;
+      const uint2 h = *reinterpret_cast<const uint2 *>(src);
+      const uint2 lo = *reinterpret_cast<const uint2 *>(src + 64);
+      v[0] = (h.x & 0xffffu) | (lo.x << 16);
+      v[1] = (h.x >> 16) | (lo.x & 0xffff0000u);
+      v[2] = (h.y & 0xffffu) | (lo.y << 16);
+      v[3] = (h.y >> 16) | (lo.y & 0xffff0000u);
+    } else {
+      v = *reinterpret_cast<const u32x4 *>(z + (x0 + r) * row_bytes + 16 * u);
+    }
+    *reinterpret_cast<u32x4 *>(rows + r * l_pad + 4 * u) = v;
+  }
+  __syncthreads();
+  constexpr int kS = SPLIT ? 8 : 4;  // samples per thread step
+  const int64_t steps = l_pad / kS;
+  for (int s = 0; s < copies; ++s) {
+    const int32_t *pr = perms + (p0 + s) * l;
+    unsigned char *dst = zp + s * zp_stride + x0 * row_bytes;
+    for (int64_t q = threadIdx.x; q < steps; q += blockDim.x) {
+      const int64_t k0 = kS * q;
+      int32_t idx[kS];
+#pragma unroll
+      for (int e = 0; e < kS; ++e) idx[e] = (k0 + e < l) ? pr[k0 + e] : -1;
+      for (int r = 0; r < nr; ++r) {
+        const uint32_t *row = rows + r * l_pad;
+        uint32_t w[kS];
+#pragma unroll
+        for (int e = 0; e < kS; ++e) w[e] = idx[e] >= 0 ? row[idx[e]] : 0u;
+        unsigned char *d = dst + r * row_bytes;
+        if constexpr (SPLIT) {
+          const int64_t c = k0 >> 5, u = (k0 & 31) >> 3;  // chunk, unit of 8 samples
+          u32x4 hv, lv;
+#pragma unroll
+          for (int e2 = 0; e2 < 4; ++e2) {
+            hv[e2] = (w[2 * e2] & 0xffffu) | (w[2 * e2 + 1] << 16);
+            lv[e2] = (w[2 * e2] >> 16) | (w[2 * e2 + 1] & 0xffff0000u);
+          }
+          *reinterpret_cast<u32x4 *>(d + c * 128 + 16 * u) = hv;
+          *reinterpret_cast<u32x4 *>(d + c * 128 + 64 + 16 * u) = lv;
+        } else {
+          *reinterpret_cast<u32x4 *>(d + 16 * q) = u32x4{w[0], w[1], w[2], w[3]};
+        }
+      }
+    }
+  }
+}
+
+// The same gather for rows too long to stage (one workgroup per row and
+// copy, every sample read from memory).
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void perm_gather_kernel(const unsigned char *__restrict__ z,
                                                          int64_t row_bytes, int64_t l,
@@ -524,8 +594,10 @@ hipError_t launch_permtest_tiles(const pcc_zdesc &zd, const void *z, const int32
   int occ = tile_occupancy(amode, cfg.tile, 0);
   if (occ < 1) occ = 1;
   const int64_t m = (zd.n + cfg.tile - 1) / cfg.tile;
-  int64_t grid = cfg.grid > 0 ? cfg.grid : (int64_t)(cus > 0 ? cus : 256) * occ;
-  if (grid > m * (m + 1) / 2) grid = m * (m + 1) / 2;
+  // persistent workgroups of a tile launch (the observed r's launch has no
+  // more than its tiles)
+  const int64_t g0 = cfg.grid > 0 ? cfg.grid : (int64_t)(cus > 0 ? cus : 256) * occ;
+  const int64_t grid = std::min<int64_t>(g0, m * (m + 1) / 2);
   hipError_t e = launch_allpairs(zd, z, w.robs, cfg, (int)grid, st);
   if (e != hipSuccess) return e;
   int32_t *cnt0 = S > 1 ? w.slots : counts;
@@ -537,18 +609,55 @@ hipError_t launch_permtest_tiles(const pcc_zdesc &zd, const void *z, const int32
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const bool split = amode == PCC_SPLIT_BF16X3;
-  for (int64_t p0 = 0; p0 < P; p0 += S) {
-    const int sc = (int)std::min<int64_t>(S, P - p0);
-    if (split)
+  // rows staged per gather workgroup: as many as 128 KiB of LDS holds, at most 8
+  const int64_t row_lds = zd.l_pad * 4;
+  const int R = (int)std::min<int64_t>(8, ((int64_t)128 * 1024) / row_lds);
+  if (R >= 1) {
+    const size_t lds = (size_t)R * (size_t)row_lds;
+    const void *gk = split ? (const void *)perm_gather_lds_kernel<true>
+                           : (const void *)perm_gather_lds_kernel<false>;
+    if ((e = hipFuncSetAttribute(gk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+        hipSuccess)
+      return e;
+  }
+  // tile jobs of one copy, and workgroups of a tile launch
+  const int64_t T = m * (m + 1) / 2;
+  const int64_t G = std::max<int64_t>(1, g0);
+  for (int64_t p0 = 0, sc = 0; p0 < P; p0 += sc) {
+    // copies in this launch: the count (at most S) whose jobs fill the
+    // grid's rounds best, the larger one on a tie
+    sc = 1;
+    double best = 0.0;
+    for (int64_t c = 1; c <= std::min<int64_t>(S, P - p0); ++c) {
+      const int64_t jobs = c * T;
+      const double fill = (double)jobs / (double)(((jobs + G - 1) / G) * G);
+      if (fill >= best) {
+        best = fill;
+        sc = c;
+      }
+    }
+    if (R >= 1) {
+      const size_t lds = (size_t)R * (size_t)row_lds;
+      const unsigned blocks = (unsigned)((zd.n_pad + R - 1) / R);
+      if (split)
+        hipLaunchKernelGGL(perm_gather_lds_kernel<true>, dim3(blocks), dim3(256), lds, st,
+                           (const unsigned char *)z, zd.row_bytes, zd.n_pad, zd.l, zd.l_pad, R,
+                           perms, p0, (int)sc, w.zp, zd.bytes);
+      else
+        hipLaunchKernelGGL(perm_gather_lds_kernel<false>, dim3(blocks), dim3(256), lds, st,
+                           (const unsigned char *)z, zd.row_bytes, zd.n_pad, zd.l, zd.l_pad, R,
+                           perms, p0, (int)sc, w.zp, zd.bytes);
+    } else if (split) {
       hipLaunchKernelGGL(perm_gather_kernel<true>, dim3((unsigned)zd.n_pad, (unsigned)sc), dim3(256),
                          0, st, (const unsigned char *)z, zd.row_bytes, zd.l, zd.l_pad, perms, p0,
                          w.zp, zd.bytes);
-    else
+    } else {
       hipLaunchKernelGGL(perm_gather_kernel<false>, dim3((unsigned)zd.n_pad, (unsigned)sc),
                          dim3(256), 0, st, (const unsigned char *)z, zd.row_bytes, zd.l, zd.l_pad,
                          perms, p0, w.zp, zd.bytes);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = launch_perm_tiles(zd, z, w.zp, zd.bytes, w.robs, cnt0, cnt_stride, sc, cfg, cus, st);
+    e = launch_perm_tiles(zd, z, w.zp, zd.bytes, w.robs, cnt0, cnt_stride, (int)sc, cfg, cus, st);
     if (e != hipSuccess) return e;
   }
   const int nblocks = (int)std::min<int64_t>((np + 255) / 256, 4096);

@@ -61,7 +61,10 @@ typedef __attribute__((address_space(3))) void lds_void;
 //   EPI_PACKED_F64  symmetric, packed, FP64 r (FP64 mode only)
 //   EPI_PERM        symmetric job matrix of Z against a column-permuted copy
 //                   of Z: cnt[J'] += 1 where |r| >= |robs[J']| (permutation
-//                   test; the job owning a tile is its only writer)
+//                   test; the job owning a tile is the only writer of its
+//                   counts in a launch, so an atomic add with no return
+//                   value serves as the increment and saves the load of a
+//                   read-modify-write)
 enum { EPI_PACKED = 0, EPI_EDGES = 1, EPI_RECT = 2, EPI_RECT_EDGES = 3, EPI_PACKED_F64 = 4,
        EPI_PERM = 5 };
 
@@ -144,10 +147,6 @@ template <int EPI> struct Epi {
                                               T rv) {
     if constexpr (EPI == EPI_PACKED_F64) {
       ea.r64[rb + x] = (double)rv;
-    } else if constexpr (EPI == EPI_PERM) {
-      // NaN on either side never counts (the caller marks such pairs)
-      const float ro = ea.robs[rb + x];
-      if ((rv < (T)0 ? -rv : rv) >= (T)(ro < 0.0f ? -ro : ro)) ea.cnt[rb + x] += 1;
     } else if constexpr (kEdges) {
       if ((rv < (T)0 ? -rv : rv) >= (T)ea.thr) {
         const unsigned long long s = atomicAdd(ea.count, 1ull);
@@ -363,17 +362,56 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
   // register v holds row 8*(v/4) + 4*g + (v%4) of the block.
   const int64_t y0 = yt * TILE + wr * WTR;
   const int64_t x0 = xt * TILE + wc * WTC;
+  if constexpr (EPI == EPI_PERM) {
+    // Counting epilogue: the observed r of half a block row (8 rows) is
+    // loaded whole before any of its counts is touched, so the loads share
+    // one wait (one after each count update would wait for that update to
+    // complete as well).  Half rows keep the loaded values within registers.
 #pragma unroll
-  for (int p = 0; p < NBR; ++p) {
+    for (int p = 0; p < NBR; ++p) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-      const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+      for (int h = 0; h < 2; ++h) {
+        float ro[8][NBC];
 #pragma unroll
-      for (int q = 0; q < NBC; ++q) {
-        const int64_t x = x0 + q * 32 + i;
-        if (Epi<EPI>::keep(zv, y, x))
-          Epi<EPI>::emit(ea, rbase, y, x, clamp_unit(acc[p][q][v] * zv.scale));
+        for (int vv = 0; vv < 8; ++vv) {
+          const int v = 8 * h + vv;
+          const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+          const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+#pragma unroll
+          for (int q = 0; q < NBC; ++q) {
+            const int64_t x = x0 + q * 32 + i;
+            ro[vv][q] = Epi<EPI>::keep(zv, y, x) ? ea.robs[rbase + x] : __builtin_nanf("");
+          }
+        }
+#pragma unroll
+        for (int vv = 0; vv < 8; ++vv) {
+          const int v = 8 * h + vv;
+          const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+          const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+#pragma unroll
+          for (int q = 0; q < NBC; ++q) {
+            // NaN (masked cells, degenerate pairs) never counts
+            const float rv = clamp_unit(acc[p][q][v] * zv.scale);
+            if (fabsf(rv) >= fabsf(ro[vv][q]))
+              (void)__hip_atomic_fetch_add(ea.cnt + rbase + x0 + q * 32 + i, 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < NBR; ++p) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+        const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+#pragma unroll
+        for (int q = 0; q < NBC; ++q) {
+          const int64_t x = x0 + q * 32 + i;
+          if (Epi<EPI>::keep(zv, y, x))
+            Epi<EPI>::emit(ea, rbase, y, x, clamp_unit(acc[p][q][v] * zv.scale));
+        }
       }
     }
   }

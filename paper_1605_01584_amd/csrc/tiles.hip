@@ -101,7 +101,15 @@ __global__ __launch_bounds__(kTileThreads, 1) void perm_tile_kernel(PermTileArgs
   __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
   const int64_t G = gridDim.x;
   for (int64_t u = xcd_slot(blockIdx.x, G); u < a.njobs; u += G) {
-    const int64_t s = u / a.T, t = u - s * a.T;
+    // several copies per launch only when a copy has few tiles (the pairs
+    // of n profiles are then fewer than 2^26): a 32-bit division, its result
+    // said to be wave-uniform, which keeps the job decode in scalar registers
+    // (a 64-bit division here made the 256-wide kernel spill in its K loop)
+    int64_t s = 0, t = u;
+    if (a.njobs > a.T) {
+      s = __builtin_amdgcn_readfirstlane((uint32_t)u / (uint32_t)a.T);
+      t = u - s * a.T;
+    }
     const Cell tc = tile_of_job(a.m, a.order, a.band, t);
     ZView zv = a.zv;
     zv.zc = a.zp + s * a.zp_stride;

@@ -54,10 +54,12 @@ def _check(got, X, perms, I, J, mode):
 
 @pytest.mark.parametrize("mode", ["fp32", "split"])
 @pytest.mark.parametrize("n,l,P", [(200, 5000, 24), (300, 609, 25), (257, 1000, 33),
-                                   (130, 2049, 7), (2, 700, 5)])
+                                   (130, 2049, 7), (2, 700, 5), (50, 20000, 4), (40, 33000, 3)])
 def test_long_rows_all_pairs(mode, n, l, P):
     """Rows past the LDS kernel's limit, through pcc_permtest (which takes the
-    tiled form for them) on every pair."""
+    tiled form for them) on every pair.  The gather of permuted copies stages
+    8 rows in LDS up to 4096 samples, one row up to 32768 samples, and reads
+    longer rows from memory (l = 33000)."""
     import paper_1605_01584_amd as pcc
     zd = pcc.z_layout(n, l, mode)
     assert zd.l_pad > pcc.permtest_max_l(mode)
