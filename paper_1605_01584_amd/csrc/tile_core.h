@@ -112,12 +112,24 @@ template <int TILE> struct TileShape {
 };
 
 __device__ __forceinline__ float clamp_unit(float r) {
-  // NaN passes through (both comparisons false).
-  return r > 1.0f ? 1.0f : (r < -1.0f ? -1.0f : r);
+  // median of (r, -1, 1), then NaN restored (the median of a NaN and two
+  // numbers need not be NaN): three instructions, NaN passes through
+  const float c = __builtin_amdgcn_fmed3f(r, -1.0f, 1.0f);
+  return r == r ? c : r;
 }
 
 __device__ __forceinline__ double clamp_unit(double r) {
   return r > 1.0 ? 1.0 : (r < -1.0 ? -1.0 : r);
+}
+
+// Accumulator -> r: the FP16 layout holds z * sqrt(l), so its products are
+// scaled by 1/l; every other layout's accumulator is r itself.
+template <int MODE>
+__device__ __forceinline__ float acc_to_r(float a, float scale) {
+  if constexpr (MODE == PCC_FP16)
+    return clamp_unit(a * scale);
+  else
+    return clamp_unit(a);
 }
 
 // Mask, output row base and store of one r value for epilogue kind EPI.
@@ -125,18 +137,39 @@ template <int EPI> struct Epi {
   static constexpr bool kRect = EPI == EPI_RECT || EPI == EPI_RECT_EDGES;
   static constexpr bool kEdges = EPI == EPI_EDGES || EPI == EPI_RECT_EDGES;
   // Packed: row y of the strict upper triangle starts at F_{n-1}(y) - y - 1 + x.
+  // Profile indices are below 2^31, so the products are 32 x 32 -> 64 bits
+  // (one multiply-add) and the masks compare 32-bit values.
   static __device__ __forceinline__ int64_t rowbase(const ZView &zv, const EpiArgs &ea,
-                                                    int64_t y) {
-    if constexpr (kRect)
-      return y * ea.ldr;
-    else
-      return tri_F(zv.n - 1, y) - 1 - y - ea.roff;
+                                                    uint32_t y) {
+    if constexpr (kRect) {
+      return (int64_t)((uint64_t)y * (uint64_t)ea.ldr);
+    } else {
+      // F_{n-1}(y) = y (2(n-1) - y + 1) / 2, both factors below 2^32
+      const uint32_t f = 2u * (uint32_t)zv.n - 1u - y;
+      return (int64_t)(((uint64_t)y * (uint64_t)f) >> 1) - 1 - (int64_t)y - ea.roff;
+    }
   }
-  static __device__ __forceinline__ bool keep(const ZView &zv, int64_t y, int64_t x) {
+  // rowbase(y + 1) - rowbase(y): the row pitch, or the length n - 1 - y of
+  // packed row y less the one-column shift of the next row
+  static __device__ __forceinline__ int64_t row_step(const ZView &zv, const EpiArgs &ea,
+                                                     uint32_t y) {
     if constexpr (kRect)
-      return y < zv.n && x < zv.nc;
+      return ea.ldr;
     else
-      return y < x && x < zv.n;
+      return (int64_t)(int32_t)((uint32_t)zv.n - 2u - y);
+  }
+  static __device__ __forceinline__ bool keep(const ZView &zv, uint32_t y, uint32_t x) {
+    if constexpr (kRect)
+      return y < (uint32_t)zv.n && x < (uint32_t)zv.nc;
+    else
+      return y < x && x < (uint32_t)zv.n;
+  }
+  // Every cell of the TILE x TILE tile at rows ya.., columns xa.. is kept.
+  static __device__ __forceinline__ bool full(const ZView &zv, int64_t ya, int64_t xa, int TILE) {
+    if constexpr (kRect)
+      return ya + TILE <= zv.n && xa + TILE <= zv.nc;
+    else
+      return ya + TILE <= xa && xa + TILE <= zv.n;
   }
   // rv is already clamped (NaN kept: it fails |rv| >= thr).  r is stored
   // with ordinary (L2 write-back) stores: nontemporal ones measured about 1%
@@ -362,6 +395,9 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
   // register v holds row 8*(v/4) + 4*g + (v%4) of the block.
   const int64_t y0 = yt * TILE + wr * WTR;
   const int64_t x0 = xt * TILE + wc * WTC;
+  // Tiles wholly inside the kept region (all but the diagonal ones and the
+  // last column or row) store every value without a per-value mask.
+  const bool whole = Epi<EPI>::full(zv, yt * TILE, xt * TILE, TILE);
   if constexpr (EPI == EPI_PERM) {
     // Counting epilogue: the observed r of half a block row (8 rows) is
     // loaded whole before any of its counts is touched, so the loads share
@@ -375,25 +411,25 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
 #pragma unroll
         for (int vv = 0; vv < 8; ++vv) {
           const int v = 8 * h + vv;
-          const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-          const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+          const uint32_t y = (uint32_t)(y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3));
+          const float *rrow = ea.robs + Epi<EPI>::rowbase(zv, ea, y) + x0 + i;
 #pragma unroll
           for (int q = 0; q < NBC; ++q) {
-            const int64_t x = x0 + q * 32 + i;
-            ro[vv][q] = Epi<EPI>::keep(zv, y, x) ? ea.robs[rbase + x] : __builtin_nanf("");
+            const uint32_t x = (uint32_t)(x0 + q * 32 + i);
+            ro[vv][q] = (whole || Epi<EPI>::keep(zv, y, x)) ? rrow[q * 32] : __builtin_nanf("");
           }
         }
 #pragma unroll
         for (int vv = 0; vv < 8; ++vv) {
           const int v = 8 * h + vv;
-          const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-          const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+          const uint32_t y = (uint32_t)(y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3));
+          int32_t *crow = ea.cnt + Epi<EPI>::rowbase(zv, ea, y) + x0 + i;
 #pragma unroll
           for (int q = 0; q < NBC; ++q) {
             // NaN (masked cells, degenerate pairs) never counts
-            const float rv = clamp_unit(acc[p][q][v] * zv.scale);
+            const float rv = acc_to_r<MODE>(acc[p][q][v], zv.scale);
             if (fabsf(rv) >= fabsf(ro[vv][q]))
-              (void)__hip_atomic_fetch_add(ea.cnt + rbase + x0 + q * 32 + i, 1, __ATOMIC_RELAXED,
+              (void)__hip_atomic_fetch_add(crow + q * 32, 1, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
           }
         }
@@ -403,14 +439,28 @@ __device__ __forceinline__ void do_tile(const ZView &zv, const EpiArgs &ea, int6
 #pragma unroll
     for (int p = 0; p < NBR; ++p) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t y = y0 + p * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-        const int64_t rbase = Epi<EPI>::rowbase(zv, ea, y);
+      for (int j = 0; j < 4; ++j) {
+        // rows y4 .. y4 + 3 (registers v = 4j .. 4j + 3): the first row's
+        // start computed, the next ones stepped by the row lengths
+        const uint32_t y4 = (uint32_t)(y0 + p * 32 + 8 * j + 4 * g);
+        int64_t rbase = Epi<EPI>::rowbase(zv, ea, y4);
 #pragma unroll
-        for (int q = 0; q < NBC; ++q) {
-          const int64_t x = x0 + q * 32 + i;
-          if (Epi<EPI>::keep(zv, y, x))
-            Epi<EPI>::emit(ea, rbase, y, x, clamp_unit(acc[p][q][v] * zv.scale));
+        for (int t = 0; t < 4; ++t) {
+          const int v = 4 * j + t;
+          const uint32_t y = y4 + t;
+          if (t > 0) rbase += Epi<EPI>::row_step(zv, ea, y - 1);
+          if (whole) {
+#pragma unroll
+            for (int q = 0; q < NBC; ++q)
+              Epi<EPI>::emit(ea, rbase, y, x0 + q * 32 + i, acc_to_r<MODE>(acc[p][q][v], zv.scale));
+          } else {
+#pragma unroll
+            for (int q = 0; q < NBC; ++q) {
+              const uint32_t x = (uint32_t)(x0 + q * 32 + i);
+              if (Epi<EPI>::keep(zv, y, x))
+                Epi<EPI>::emit(ea, rbase, y, x, acc_to_r<MODE>(acc[p][q][v], zv.scale));
+            }
+          }
         }
       }
     }
