@@ -45,7 +45,6 @@ struct BatchDesc {
 };
 
 constexpr size_t kCounterBytes = 256;
-constexpr int kCounterStride = 16;  // the two job counters, 128 bytes apart
 
 // Workspace: [job counters | descriptor table | job0 of every dataset |
 // first row group of every dataset], each part 256-byte aligned.  A
@@ -96,10 +95,7 @@ __device__ __forceinline__ int find_desc(const int64_t *keys, int D, int64_t key
   return lo;
 }
 
-__global__ void batch_zero_kernel(unsigned long long *counters) {
-  counters[0] = 0ull;
-  counters[kCounterStride] = 0ull;
-}
+__global__ void batch_zero_kernel(unsigned long long *counter) { *counter = 0ull; }
 
 // Row normalisation of a batch.  One kernel serves every input variant of
 // the batch (FP32/FP64, vector or scalar loads), with the single-matrix
@@ -164,17 +160,21 @@ __global__ __launch_bounds__(256) void batch_norm_kernel(const BatchDesc *__rest
   }
 }
 
-// All-pairs jobs of the datasets that use one tile size: tile ids drawn
-// from a device counter over the datasets' concatenated job spaces.
-template <int MODE, int TILE>
+// All-pairs jobs of every dataset, both tile sizes: tile ids drawn from one
+// device counter over the datasets' concatenated job spaces, datasets in
+// order of decreasing work per job (so the long jobs go first and the short
+// ones fill the end).  LDS is sized for the 256-wide tiles; a 128-wide job
+// uses the first half of it.
+template <int MODE>
 __global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const BatchDesc *__restrict__ descs,
                                                             const int64_t *__restrict__ job0s,
                                                             int D, int64_t total_jobs,
                                                             unsigned long long *counter) {
-  __shared__ u32x4 smem[TileShape<TILE>::LDS_UNITS];
+  __shared__ u32x4 smem[TileShape<256>::LDS_UNITS];
   __shared__ int64_t jslot;
   __shared__ int64_t skeys[kKeysInLds];
   const int64_t *keys = load_keys(job0s, D, skeys);
+  int prev = 0;  // tile size of the previous job
   for (;;) {
     if (threadIdx.x == 0) jslot = (int64_t)atomicAdd(counter, 1ull);
     __syncthreads();
@@ -187,42 +187,34 @@ __global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const Batch
     ZView zv{d.z, d.row_bytes, d.n, d.nchunks, d.scale, d.z, d.n};
     EpiArgs ea{};
     ea.r = d.r;
-    // short split rows hold FP32 z (same LDS layout, so no wait between the
-    // two kinds of tile)
-    if (MODE == PCC_SPLIT_BF16X3 && d.nchunks * 32 <= kSplitFp32MaxLPad)
-      do_tile<PCC_FP32, TILE, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
-    else
-      do_tile<MODE, TILE, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+    // short split rows hold FP32 z (same LDS layout as the split rows)
+    const bool f32 = MODE == PCC_SPLIT_BF16X3 && d.nchunks * 32 <= kSplitFp32MaxLPad;
+    const int kind = d.tile;
+    // the last stage copy of a call may still be in flight into LDS units
+    // that a job of the other tile size lays out differently
+    if (prev != 0 && prev != kind) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    prev = kind;
+    if (kind == 256) {
+      if (f32)
+        do_tile<PCC_FP32, 256, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+      else
+        do_tile<MODE, 256, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+    } else {
+      if (f32)
+        do_tile<PCC_FP32, 128, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+      else
+        do_tile<MODE, 128, EPI_PACKED>(zv, ea, tc.y, tc.x, smem);
+    }
     // do_tile begins with a barrier, which every thread reaches after it has
     // read jslot, so thread 0 may overwrite jslot at the next iteration.
   }
 }
 
-template <int MODE, int TILE>
-hipError_t launch_tiles(const BatchDesc *descs, const int64_t *job0s, int D, int64_t jobs,
-                        unsigned long long *counter, int cus, hipStream_t st) {
-  if (D <= 0 || jobs <= 0) return hipSuccess;
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_tile_kernel<MODE, TILE>,
-                                                   kTileThreads, 0) != hipSuccess ||
-      occ < 1)
-    occ = 1;
-  int64_t grid = (int64_t)cus * occ;
-  if (grid > jobs) grid = jobs;
-  hipLaunchKernelGGL((batch_tile_kernel<MODE, TILE>), dim3((unsigned)grid), dim3(kTileThreads), 0,
-                     st, descs, job0s, D, jobs, counter);
-  return hipGetLastError();
-}
-
-// descs[0, d256) use 256-wide tiles (jobs256 jobs, counters[0]), the rest
-// 128-wide (jobs128 jobs, counters[kCounterStride]); job0 restarts at 0 in
-// each group.
-
 template <int MODE>
 hipError_t launch_batch(const BatchDesc *descs, const int64_t *job0s, const int64_t *grp0s, int D,
-                        int d256, int64_t total_groups, int64_t jobs256, int64_t jobs128,
-                        unsigned long long *counters, int cus, hipStream_t st) {
-  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(1), 0, st, counters);
+                        int64_t total_groups, int64_t jobs, unsigned long long *counter, int cus,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(1), 0, st, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // grid-stride over row groups: a few workgroups per compute unit, each
@@ -232,11 +224,17 @@ hipError_t launch_batch(const BatchDesc *descs, const int64_t *job0s, const int6
   hipLaunchKernelGGL((batch_norm_kernel<MODE>), dim3((unsigned)nblocks), dim3(256), 0, st, descs,
                      grp0s, D, total_groups);
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = launch_tiles<MODE, 256>(descs, job0s, d256, jobs256, counters, cus, st);
-  if (e != hipSuccess) return e;
-  return launch_tiles<MODE, 128>(descs + d256, job0s + d256, D - d256, jobs128,
-                                 counters + kCounterStride, cus, st);
+  if (e != hipSuccess || D <= 0 || jobs <= 0) return e;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_tile_kernel<MODE>, kTileThreads,
+                                                   0) != hipSuccess ||
+      occ < 1)
+    occ = 1;
+  int64_t grid = (int64_t)cus * occ;
+  if (grid > jobs) grid = jobs;
+  hipLaunchKernelGGL((batch_tile_kernel<MODE>), dim3((unsigned)grid), dim3(kTileThreads), 0, st,
+                     descs, job0s, D, jobs, counter);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -249,14 +247,13 @@ namespace {
 
 // Totals of a batch after build_batch.
 struct BatchSums {
-  int64_t jobs256, jobs128, groups, rows;
-  int d256;  // datasets [0, d256) use 256-wide tiles
+  int64_t jobs, groups, rows;
 };
 
 // Host work of a batch: validate the items, fill one descriptor per dataset,
-// order them (256-wide tiles first, one kernel each; longest jobs first
-// within a group: the work of one job grows with l_pad for a given tile) and
-// give each its first job, row and row group.  ds holds D descriptors.
+// order them by decreasing work per job (l_pad * tile^2: the job counter
+// hands out the long jobs first) and give each its first job, row and row
+// group.  ds holds D descriptors.
 // Stable ordering, by insertion for the few datasets of a call that may not
 // allocate and by std::stable_sort otherwise: either way the order is the
 // one the comparison fixes, so both entry points build the same table.
@@ -297,8 +294,7 @@ pcc_status build_batch(int32_t D, const pcc_batch_item *items, pcc_mode_t mode, 
     d.out_scale = (mode == PCC_FP16) ? sqrt((double)zd.l) : 1.0;
   }
   const auto before = [](const BatchDesc &a, const BatchDesc &b) {
-    if (a.tile != b.tile) return a.tile > b.tile;
-    return a.l_pad > b.l_pad;
+    return a.l_pad * a.tile * a.tile > b.l_pad * b.tile * b.tile;
   };
   if (D <= kStaticMaxD) {
     for (int32_t k = 1; k < D; ++k) {
@@ -310,15 +306,13 @@ pcc_status build_batch(int32_t D, const pcc_batch_item *items, pcc_mode_t mode, 
   } else {
     std::stable_sort(ds, ds + D, before);
   }
-  BatchSums t{0, 0, 0, 0, 0};
+  BatchSums t{0, 0, 0};
   for (int32_t k = 0; k < D; ++k) {
     BatchDesc &d = ds[k];
-    int64_t &jobs = (d.tile == 256) ? t.jobs256 : t.jobs128;
-    if (d.tile == 256) ++t.d256;
-    d.job0 = jobs;
+    d.job0 = t.jobs;
     d.row0 = t.rows;
     d.grp0 = t.groups;
-    jobs += d.m * (d.m + 1) / 2;
+    t.jobs += d.m * (d.m + 1) / 2;
     t.rows += d.n_pad;
     t.groups += d.n_pad / (64 / d.lanes);  // n_pad is a multiple of 256
   }
@@ -348,8 +342,7 @@ template <int MODE>
 hipError_t launch_batch_mode(const BatchDesc *descs, const int64_t *job0s, const int64_t *grp0s,
                              int D, const BatchSums &t, unsigned long long *counters, int cus,
                              hipStream_t st) {
-  return launch_batch<MODE>(descs, job0s, grp0s, D, t.d256, t.groups, t.jobs256, t.jobs128,
-                            counters, cus, st);
+  return launch_batch<MODE>(descs, job0s, grp0s, D, t.groups, t.jobs, counters, cus, st);
 }
 
 hipError_t launch_batch_any(int mode, const BatchDesc *descs, const int64_t *job0s,
@@ -448,7 +441,7 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
   BatchSums t;
   const pcc_status bs = build_batch(D, items, mode, ds.data(), &t);
   if (bs != PCC_OK) return bs;
-  const int64_t jobs = t.jobs256 + t.jobs128;
+  const int64_t jobs = t.jobs;
   hipStream_t st = (hipStream_t)stream;
   const WsParts wp = ws_parts(workspace, D);
   std::vector<int64_t> keys(2 * (size_t)D);

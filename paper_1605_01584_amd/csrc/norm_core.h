@@ -23,6 +23,9 @@
 
 namespace pcc {
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 // Sum over the G lanes of a group (G a power of two dividing 64; every lane
 // of the group takes part).
 __device__ __forceinline__ double group_sum(double v, int G) {
@@ -111,18 +114,21 @@ __device__ __forceinline__ void store_unit(unsigned char *zr, int64_t u, const d
     }
     *reinterpret_cast<uint4 *>(zr + u * 16) = make_uint4(w[0], w[1], w[2], w[3]);
   } else {  // split: hi = bf16(z), lo = bf16(z - hi), hi and lo halves of a chunk
+    // Each value is rounded to FP32 first, then to BF16 (round to nearest
+    // even, two values per v_cvt_pk_bf16_f32).  The empty asm keeps the FP32
+    // value: the compiler would otherwise fuse the two roundings into one.
     uint32_t wh[4], wl[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      uint16_t h[2], lo[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const double zz = z[2 * q + s];
-        h[s] = f32_to_bf16_bits((float)zz);
-        lo[s] = f32_to_bf16_bits((float)(zz - (double)bf16_bits_to_f32(h[s])));
-      }
-      wh[q] = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-      wl[q] = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
+      f32x2_t zf = {(float)z[2 * q], (float)z[2 * q + 1]};
+      asm volatile("" : "+v"(zf));
+      const bf16x2_t h = __builtin_convertvector(zf, bf16x2_t);
+      const uint32_t hw = __builtin_bit_cast(uint32_t, h);
+      f32x2_t rf = {(float)(z[2 * q] - (double)__builtin_bit_cast(float, hw << 16)),
+                    (float)(z[2 * q + 1] - (double)__builtin_bit_cast(float, hw & 0xffff0000u))};
+      asm volatile("" : "+v"(rf));
+      wh[q] = hw;
+      wl[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(rf, bf16x2_t));
     }
     const int64_t c = u >> 2, part = u & 3;
     *reinterpret_cast<uint4 *>(zr + c * 128 + part * 16) = make_uint4(wh[0], wh[1], wh[2], wh[3]);
