@@ -221,8 +221,9 @@ pcc_status pcc_allpairs_f64(const pcc_zdesc *zd, const void *z, double *r,
  *   r_host   host, n(n-1)/2 floats, the packed triangle as pcc_allpairs
  *            writes it.  Should be pinned (hipHostMalloc) for asynchronous
  *            copies.
- *   dev_buf  device, at least pcc_stream_buffer_bytes(zd, cfg,
- *            rows_per_pass) bytes (two pass buffers).
+ *   dev_buf  device, 16-byte aligned, at least pcc_stream_buffer_bytes(zd,
+ *            cfg, rows_per_pass) bytes (two pass buffers); else
+ *            PCC_E_WORKSPACE.
  * Blocking: returns after every pass has landed in r_host.  compute_stream
  * and copy_stream may be equal (no overlap then).  Creates and destroys
  * four HIP events per call; allocates no memory. */
@@ -289,8 +290,8 @@ pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
  * P permutations; jobs are 32 x 32 pair blocks whose two profile panels
  * stay in LDS for all P permutations; `workspace` is unused (may be NULL).
  * Longer rows: the tiled form of pcc_permtest_tiles with the default
- * schedule; `workspace` must hold pcc_workspace_size(zd, 2) bytes (NULL
- * gives PCC_E_WORKSPACE).
+ * schedule; `workspace` must hold pcc_workspace_size(zd, 2) bytes and be
+ * 256-byte aligned (NULL or misaligned gives PCC_E_WORKSPACE).
  *   perms  device int32, P rows of l entries, each a permutation of 0..l-1.
  *          Not checked on the device: an entry outside [0, l) reads other
  *          data of the job (LDS of the workgroup, or the row of Z in the
@@ -320,8 +321,8 @@ pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
  * counts as for pcc_permtest; the r of a pair is the all-pairs kernel's on
  * this schedule (the LDS kernel rounds in another order, so counts of the
  * two forms can differ where some |r_p| lies within rounding of |r_obs|).
- * workspace: device, workspace_bytes >= pcc_workspace_size(zd, 3), else
- * PCC_E_WORKSPACE.  Modes as pcc_permtest. */
+ * workspace: device, 256-byte aligned, workspace_bytes >=
+ * pcc_workspace_size(zd, 3), else PCC_E_WORKSPACE.  Modes as pcc_permtest. */
 pcc_status pcc_permtest_tiles(const pcc_zdesc *zd, const void *z, const int32_t *perms,
                               int32_t P, int32_t *counts, const pcc_tile_cfg *cfg,
                               void *workspace, size_t workspace_bytes, void *stream);
@@ -350,7 +351,8 @@ typedef struct {
 
 typedef struct pcc_batch_plan pcc_batch_plan;
 
-/* Workspace bytes a batch of D items needs. */
+/* Workspace bytes a batch of D items needs (the workspace must be 256-byte
+ * aligned; pcc_batch_plan_create gives PCC_E_WORKSPACE otherwise). */
 size_t pcc_batch_workspace_size(int32_t D);
 
 /* Build a plan (host work + one synchronous upload of the descriptor table

@@ -279,7 +279,8 @@ pcc_status pcc_allpairs_to_host(const pcc_zdesc *zd, const void *z, float *r_hos
   // a pass must be a whole number of bands to be a contiguous id range
   if (c.order == 1 && c.band > 1 && rows_per_pass % c.band != 0) return PCC_E_ARG;
   const size_t need = pcc_stream_buffer_bytes(zd, &c, rows_per_pass);
-  if (!dev_buf || dev_buf_bytes < need) return PCC_E_WORKSPACE;
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 15) || dev_buf_bytes < need)
+    return PCC_E_WORKSPACE;
   const int64_t n = zd->n, T = c.tile, m = (n + T - 1) / T;
   float *buf[2] = {(float *)dev_buf, (float *)dev_buf + need / 2 / sizeof(float)};
   hipStream_t cs = (hipStream_t)compute_stream, xs = (hipStream_t)copy_stream;
@@ -434,7 +435,7 @@ pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z, const int32_t *perms
   const int cus = device_cus();
   if (zd->l_pad > permtest_max_l(zd->mode)) {
     // rows too long for the LDS kernel: the tiled form
-    if (!workspace) return PCC_E_WORKSPACE;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return PCC_E_WORKSPACE;
     const pcc_tile_cfg c = perm_default_cfg(*zd);
     return hip_status(launch_permtest_tiles(*zd, z, perms, P, counts, workspace, c, cus,
                                             (hipStream_t)stream));
@@ -456,7 +457,9 @@ pcc_status pcc_permtest_tiles(const pcc_zdesc *zd, const void *z, const int32_t 
     s = check_cfg(*zd, cfg, c);
     if (s != PCC_OK) return s;
   }
-  if (!workspace || workspace_bytes < permtest_tiles_workspace(*zd)) return PCC_E_WORKSPACE;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) ||
+      workspace_bytes < permtest_tiles_workspace(*zd))
+    return PCC_E_WORKSPACE;
   return hip_status(launch_permtest_tiles(*zd, z, perms, P, counts, workspace, c, device_cus(),
                                           (hipStream_t)stream));
 }

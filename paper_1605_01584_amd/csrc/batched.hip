@@ -436,7 +436,9 @@ pcc_status pcc_batch_plan_create(int32_t D, const pcc_batch_item *items, pcc_mod
   if (!plan || D < 1 || !items) return PCC_E_ARG;
   *plan = nullptr;
   if (mode < PCC_FP32 || mode > PCC_FP16) return PCC_E_MODE;
-  if (!workspace || workspace_bytes < pcc_batch_workspace_size(D)) return PCC_E_WORKSPACE;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) ||
+      workspace_bytes < pcc_batch_workspace_size(D))
+    return PCC_E_WORKSPACE;
   std::vector<BatchDesc> ds((size_t)D);
   BatchSums t;
   const pcc_status bs = build_batch(D, items, mode, ds.data(), &t);

@@ -122,6 +122,10 @@ def test_host_argument_errors_return_before_launch():
                                   None) == pcc.PCC_E_WORKSPACE
     assert lib.pcc_permtest_tiles(ctypes.byref(zl), fake, fake, 3, fake, None, None, need,
                                   None) == pcc.PCC_E_WORKSPACE
+    odd = ctypes.c_void_p(0x1000 + 64)   # not 256-byte aligned
+    assert lib.pcc_permtest_tiles(ctypes.byref(zl), fake, fake, 3, fake, None, odd, need,
+                                  None) == pcc.PCC_E_WORKSPACE
+    assert lib.pcc_permtest(ctypes.byref(zl), fake, fake, 3, fake, odd, None) == pcc.PCC_E_WORKSPACE
     bad = pcc.TileCfg(64, 0, 1, 0)
     assert lib.pcc_permtest_tiles(ctypes.byref(zl), fake, fake, 3, fake, ctypes.byref(bad), fake,
                                   need, None) == pcc.PCC_E_ARG
@@ -134,6 +138,8 @@ def test_host_argument_errors_return_before_launch():
     items = (pcc.BatchItem * 1)()
     assert lib.pcc_batch_plan_create(0, items, 1, fake, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_ARG
     assert lib.pcc_batch_plan_create(1, items, 1, None, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_WORKSPACE
+    assert lib.pcc_batch_plan_create(1, items, 1, ctypes.c_void_p(0x1000 + 8), 1 << 20, None,
+                                     ctypes.byref(plan)) == pcc.PCC_E_WORKSPACE
     assert lib.pcc_batch_plan_create(1, items, 1, fake, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_ARG
     assert lib.pcc_batch_plan_create(1, items, 9, fake, 1 << 20, None, ctypes.byref(plan)) == pcc.PCC_E_MODE
     assert lib.pcc_batch_plan_launch(None, None) == pcc.PCC_E_ARG
