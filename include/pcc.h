@@ -334,11 +334,14 @@ int64_t pcc_permtest_max_l(pcc_mode_t mode);
 
 /* ---- Uneven batches -----------------------------------------------------
  * One item per dataset.  The plan uploads a descriptor table into the
- * caller's workspace and records, into one hipGraph, the batched
- * normalisation (all datasets) and one persistent all-pairs kernel whose
- * workgroups draw tile jobs from a device counter over the concatenated
- * job space (dynamic distribution with a shared integer counter, Sec.
- * III-B).  Launching the plan replays the graph on a stream. */
+ * caller's workspace and records, into one hipGraph, a counter reset and
+ * one persistent kernel: its workgroups first transform every dataset
+ * (Eq. (4)), drawing row groups from a device counter, then draw tile jobs
+ * from a second device counter over the concatenated job space (dynamic
+ * distribution with a shared integer counter, Sec. III-B).  Between the two
+ * phases a workgroup waits until every row group is done; the wait needs
+ * no co-residency of the grid (only running workgroups claim row groups) and
+ * is bounded.  Launching the plan replays the graph on a stream. */
 typedef struct {
   const void *x;      /* device input, n x l, pitch ldx, type xt */
   int64_t ldx;

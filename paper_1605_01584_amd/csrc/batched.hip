@@ -1,17 +1,18 @@
 // Uneven batches: many independent datasets (different n and l) in one
-// graph launch.  A plan uploads a descriptor table, then captures into one
-// hipGraph:
-//   1. a one-thread kernel zeroing the job counter (no memset node);
-//   2. the batched transformation, Eq. (4), a grid-stride loop of waves
-//      over the concatenated padded rows of every dataset;
-//   3. one persistent all-pairs kernel whose workgroups draw tile jobs from
-//      the shared counter (dynamic distribution through a shared integer
-//      counter, which the all-pairs framework offers for jobs of varied
-//      work) over the concatenated tile-id spaces; every dataset's ids are
-//      mapped to its tile cells by Eq. (16)-(19) with its own m.
+// persistent kernel.  A plan uploads a descriptor table, then captures into
+// one hipGraph:
+//   1. a one-thread kernel zeroing the job counters (no memset node);
+//   2. one persistent kernel that first transforms every dataset's rows,
+//      Eq. (4) (row groups drawn from a shared counter), then, once every
+//      row is done, computes the tile jobs drawn from a second counter
+//      (dynamic distribution through a shared integer counter, which the
+//      all-pairs framework offers for jobs of varied work) over the
+//      concatenated tile-id spaces; every dataset's ids are mapped to its
+//      tile cells by Eq. (16)-(19) with its own m.
 // Datasets are ordered by descending work per job so that the counter hands
 // out the long jobs first.  Each tile is computed exactly as pcc_allpairs
-// computes it with the same tile size, so batched and single results are
+// computes it with the same tile size, and each row exactly as
+// pcc_normalize transforms it, so batched and single results are
 // bit-identical.
 #include <stdlib.h>
 #include <string.h>
@@ -44,7 +45,7 @@ struct BatchDesc {
   double out_scale;  // normalisation multiplier (FP16 layout: sqrt(l))
 };
 
-constexpr size_t kCounterBytes = 256;
+constexpr size_t kCounterBytes = 512;  // four counters, 128 bytes apart
 
 // Workspace: [job counters | descriptor table | job0 of every dataset |
 // first row group of every dataset], each part 256-byte aligned.  A
@@ -95,7 +96,9 @@ __device__ __forceinline__ int find_desc(const int64_t *keys, int D, int64_t key
   return lo;
 }
 
-__global__ void batch_zero_kernel(unsigned long long *counter) { *counter = 0ull; }
+__global__ void batch_zero_kernel(unsigned long long *counters) {
+  if (threadIdx.x < 4) counters[16 * threadIdx.x] = 0ull;
+}
 
 // Row normalisation of a batch.  One kernel serves every input variant of
 // the batch (FP32/FP64, vector or scalar loads), with the single-matrix
@@ -132,51 +135,161 @@ __device__ __forceinline__ void batch_dataset_row(const BatchDesc &d, int64_t ro
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void batch_norm_kernel(const BatchDesc *__restrict__ descs,
-                                                         const int64_t *__restrict__ grp0s, int D,
-                                                         int64_t total_groups) {
-  __shared__ int64_t skeys[kKeysInLds];
-  const int64_t *keys = load_keys(grp0s, D, skeys);
-  const int64_t stride = (int64_t)gridDim.x * 4;
-  // one row group per wave: the group and its dataset are wave-uniform,
-  // which keeps the descriptor in scalar registers
-  for (int64_t W = uniform64((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)); W < total_groups;
-       W += stride) {
-    const BatchDesc &d = descs[__builtin_amdgcn_readfirstlane(find_desc(keys, D, W))];
-    const int lanes = d.lanes;
-    const int64_t row = (W - d.grp0) * (64 / lanes) + (int64_t)((threadIdx.x & 63) / lanes);
-    unsigned char *zr = d.z + row * d.row_bytes;
-    if (row >= d.n) {
-      zero_row(zr, d.row_bytes, lanes);
-      continue;
-    }
-    // a split dataset of short rows holds FP32 z, as the single-matrix
-    // transformation writes it
-    if (MODE == PCC_SPLIT_BF16X3 && d.l_pad <= kSplitFp32MaxLPad)
-      batch_dataset_row<PCC_FP32>(d, row, zr, lanes);
-    else
-      batch_dataset_row<MODE>(d, row, zr, lanes);
+// kRowsAtOnce row groups of one FP32 dataset (all rows real, each fitting
+// its lanes' registers: 32 floats per lane and row, 128 registers for the
+// four), transformed together: every row's loads first.
+constexpr int kRowsAtOnce = 4;
+
+template <int MODE, typename TIn, bool VEC>
+__device__ __forceinline__ void batch_rows_together(const BatchDesc &d, int64_t row0,
+                                                    int64_t rows_per_group, int lanes) {
+  const TIn *xr[kRowsAtOnce];
+  unsigned char *zr[kRowsAtOnce];
+#pragma unroll
+  for (int r = 0; r < kRowsAtOnce; ++r) {
+    const int64_t row = row0 + r * rows_per_group;
+    xr[r] = (const TIn *)d.x + row * d.ldx;
+    zr[r] = d.z + row * d.row_bytes;
   }
+  normalize_rows_cached<TIn, MODE, CacheOf<TIn, MODE>::C, VEC, kRowsAtOnce>(
+      xr, d.l, d.l_pad, zr, d.out_scale, lanes);
 }
 
-// All-pairs jobs of every dataset, both tile sizes: tile ids drawn from one
-// device counter over the datasets' concatenated job spaces, datasets in
-// order of decreasing work per job (so the long jobs go first and the short
-// ones fill the end).  LDS is sized for the 256-wide tiles; a 128-wide job
-// uses the first half of it.
 template <int MODE>
-__global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const BatchDesc *__restrict__ descs,
-                                                            const int64_t *__restrict__ job0s,
-                                                            int D, int64_t total_jobs,
-                                                            unsigned long long *counter) {
+__device__ __forceinline__ void batch_dataset_rows_together(const BatchDesc &d, int64_t row0,
+                                                            int64_t rows_per_group, int lanes) {
+  if ((d.ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0))
+    batch_rows_together<MODE, float, true>(d, row0, rows_per_group, lanes);
+  else
+    batch_rows_together<MODE, float, false>(d, row0, rows_per_group, lanes);
+}
+
+// Row groups [W, W + kRowsAtOnce) together when they are of one dataset,
+// all their rows are real and fit the lanes' registers; returns false (and
+// does nothing) otherwise.  Whole wave, W wave-uniform.
+template <int MODE>
+__device__ __forceinline__ bool norm_row_groups_together(const BatchDesc *__restrict__ descs,
+                                                         const int64_t *keys, int D, int64_t W) {
+  const BatchDesc &d = descs[__builtin_amdgcn_readfirstlane(find_desc(keys, D, W))];
+  const int lanes = d.lanes;
+  const int64_t rpg = 64 / lanes;  // rows per group
+  const int64_t last_row = (W + kRowsAtOnce - 1 - d.grp0) * rpg + rpg - 1;
+  const bool f32 = MODE == PCC_SPLIT_BF16X3 && d.l_pad <= kSplitFp32MaxLPad;
+  // padded units of a row against what the lanes' registers hold (32
+  // samples per lane for every mode)
+  if (d.xt != PCC_IN_F32 || last_row >= d.n || d.l_pad > (int64_t)32 * lanes) return false;
+  const int64_t row0 = (W - d.grp0) * rpg + (int64_t)((threadIdx.x & 63) / lanes);
+  if (f32)
+    batch_dataset_rows_together<PCC_FP32>(d, row0, rpg, lanes);
+  else
+    batch_dataset_rows_together<MODE>(d, row0, rpg, lanes);
+  return true;
+}
+
+// Row group W (one wave's rows) of the concatenated padded rows: its
+// dataset by binary search in keys, then the rows of the group, `lanes`
+// lanes each.  Whole wave; W and the dataset are wave-uniform, which keeps
+// the descriptor in scalar registers.
+template <int MODE>
+__device__ __forceinline__ void norm_row_group(const BatchDesc *__restrict__ descs,
+                                               const int64_t *keys, int D, int64_t W) {
+  const BatchDesc &d = descs[__builtin_amdgcn_readfirstlane(find_desc(keys, D, W))];
+  const int lanes = d.lanes;
+  const int64_t row = (W - d.grp0) * (64 / lanes) + (int64_t)((threadIdx.x & 63) / lanes);
+  unsigned char *zr = d.z + row * d.row_bytes;
+  if (row >= d.n) {
+    zero_row(zr, d.row_bytes, lanes);
+    return;
+  }
+  // a split dataset of short rows holds FP32 z, as the single-matrix
+  // transformation writes it
+  if (MODE == PCC_SPLIT_BF16X3 && d.l_pad <= kSplitFp32MaxLPad)
+    batch_dataset_row<PCC_FP32>(d, row, zr, lanes);
+  else
+    batch_dataset_row<MODE>(d, row, zr, lanes);
+}
+
+// The batch in one persistent kernel: first every workgroup transforms row
+// groups drawn from a counter (Eq. (4); runs of row groups, one per wave),
+// then, once every row group is done, tile jobs drawn from a second counter
+// (both tile sizes; LDS sized for the 256-wide tiles, a 128-wide job uses
+// the first half of it).
+//
+// The switch between the phases is a wait on a count of finished row groups.
+// Only running workgroups claim row groups, and a claimed group is finished
+// without waiting for anything, so the count always reaches the total: the
+// wait needs no guarantee that every workgroup of the grid is resident.  A
+// workgroup publishes its groups with one agent-scope release (the rows it
+// wrote leave its XCD's L2) before adding them to the count, and a workgroup
+// that has seen the full count does one agent-scope acquire before reading
+// any Z; that is one write-back and one invalidation of an XCD's L2 per
+// workgroup, all at the switch.  The wait is bounded (2 s of the real-time
+// counter): should it ever expire, the kernel goes on and counts the event
+// in counters[kTimeoutSlot] instead of hanging.
+constexpr int kClaimSlot = 0, kDoneSlot = 16, kTileSlot = 32, kTimeoutSlot = 48;
+constexpr int kClaimGroups = 16;  // row groups per claim
+constexpr uint64_t kWaitTicks = 200000000ull;  // 2 s of the 100 MHz real-time counter
+
+template <int MODE>
+__global__ __launch_bounds__(kTileThreads, 1) void batch_kernel(const BatchDesc *__restrict__ descs,
+                                                       const int64_t *__restrict__ job0s,
+                                                       const int64_t *__restrict__ grp0s, int D,
+                                                       int64_t total_groups, int64_t total_jobs,
+                                                       unsigned long long *counters) {
   __shared__ u32x4 smem[TileShape<256>::LDS_UNITS];
   __shared__ int64_t jslot;
+  __shared__ unsigned int wg_groups;
   __shared__ int64_t skeys[kKeysInLds];
+  if (threadIdx.x == 0) wg_groups = 0u;
+  __syncthreads();
+  const int64_t *gkeys = load_keys(grp0s, D, skeys);
+  // phase 1: runs of kClaimGroups consecutive row groups, one run per wave
+  // at a time (one claim per run keeps the shared counter off the path)
+  unsigned int mine = 0u;
+  for (;;) {
+    unsigned long long w = 0ull;
+    if ((threadIdx.x & 63) == 0) w = atomicAdd(counters + kClaimSlot, (unsigned long long)kClaimGroups);
+    const int64_t W0 = uniform64((int64_t)w);
+    if (W0 >= total_groups) break;
+    const int64_t W1 = W0 + kClaimGroups < total_groups ? W0 + kClaimGroups : total_groups;
+    for (int64_t W = W0; W < W1;) {
+      if (W + kRowsAtOnce <= W1 && norm_row_groups_together<MODE>(descs, gkeys, D, W)) {
+        W += kRowsAtOnce;
+      } else {
+        norm_row_group<MODE>(descs, gkeys, D, W);
+        ++W;
+      }
+    }
+    mine += (unsigned int)(W1 - W0);
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's rows are in L2
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&wg_groups, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (wg_groups) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(counters + kDoneSlot, (unsigned long long)wg_groups, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    bool late = false;
+    while (__hip_atomic_load(counters + kDoneSlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           (unsigned long long)total_groups) {
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+        late = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+    if (late) atomicAdd(counters + kTimeoutSlot, 1ull);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  // phase 2: tile jobs
   const int64_t *keys = load_keys(job0s, D, skeys);
   int prev = 0;  // tile size of the previous job
   for (;;) {
-    if (threadIdx.x == 0) jslot = (int64_t)atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) jslot = (int64_t)atomicAdd(counters + kTileSlot, 1ull);
     __syncthreads();
     // J and the dataset index are uniform across the workgroup; saying so
     // keeps the descriptor in scalar registers
@@ -212,28 +325,19 @@ __global__ __launch_bounds__(kTileThreads, 1) void batch_tile_kernel(const Batch
 
 template <int MODE>
 hipError_t launch_batch(const BatchDesc *descs, const int64_t *job0s, const int64_t *grp0s, int D,
-                        int64_t total_groups, int64_t jobs, unsigned long long *counter, int cus,
+                        int64_t total_groups, int64_t jobs, unsigned long long *counters, int cus,
                         hipStream_t st) {
-  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(1), 0, st, counter);
+  hipLaunchKernelGGL(batch_zero_kernel, dim3(1), dim3(64), 0, st, counters);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // grid-stride over row groups: a few workgroups per compute unit, each
-  // loading the key table once
-  int64_t nblocks = (total_groups + 3) / 4;
-  if (nblocks > (int64_t)cus * 8) nblocks = (int64_t)cus * 8;
-  hipLaunchKernelGGL((batch_norm_kernel<MODE>), dim3((unsigned)nblocks), dim3(256), 0, st, descs,
-                     grp0s, D, total_groups);
-  e = hipGetLastError();
-  if (e != hipSuccess || D <= 0 || jobs <= 0) return e;
+  if (e != hipSuccess || D <= 0) return e;
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_tile_kernel<MODE>, kTileThreads,
-                                                   0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel<MODE>, kTileThreads, 0) !=
+          hipSuccess ||
       occ < 1)
     occ = 1;
-  int64_t grid = (int64_t)cus * occ;
-  if (grid > jobs) grid = jobs;
-  hipLaunchKernelGGL((batch_tile_kernel<MODE>), dim3((unsigned)grid), dim3(kTileThreads), 0, st,
-                     descs, job0s, D, jobs, counter);
+  const int64_t grid = (int64_t)cus * occ;
+  hipLaunchKernelGGL((batch_kernel<MODE>), dim3((unsigned)grid), dim3(kTileThreads), 0, st, descs,
+                     job0s, grp0s, D, total_groups, jobs, counters);
   return hipGetLastError();
 }
 

@@ -279,6 +279,86 @@ __device__ __forceinline__ void normalize_row(const TIn *__restrict__ xr, int64_
   }
 }
 
+// NG rows of one matrix whose padded length fits the registers of their G
+// lanes (l_pad / E <= G * kCache), transformed exactly as normalize_row
+// transforms each of them (every sum in the same order), with the loads of
+// all NG rows issued before any row is summed, so NG rows are in flight at
+// once.  No statistics and no degenerate count (the batch keeps neither).
+template <typename TIn, int MODE, int kCache, bool VEC, int NG>
+__device__ __forceinline__ void normalize_rows_cached(const TIn *const (&xr)[NG], int64_t l64,
+                                                      int64_t l_pad,
+                                                      unsigned char *const (&zr)[NG],
+                                                      double out_scale, int G) {
+  constexpr int E = UnitOf<MODE>::E;
+  const int l = (int)l64;
+  const int units = (int)(l_pad / E);
+  const int lane = threadIdx.x & (G - 1);
+  const int nc = (units + G - 1) / G;
+  TIn cache[NG][kCache][E];
+#pragma unroll
+  for (int r = 0; r < NG; ++r)
+#pragma unroll
+    for (int c = 0; c < kCache; ++c)
+      if (c < nc) load_unit<TIn, E, VEC>(xr[r], l, (lane + G * c) * E, cache[r][c]);
+  double mean[NG], inv[NG];
+#pragma unroll
+  for (int r = 0; r < NG; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < kCache; ++c) {
+      if (c < nc) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) s += (double)cache[r][c][e];
+      }
+    }
+    mean[r] = group_sum(s, G) / (double)l;
+  }
+#pragma unroll
+  for (int r = 0; r < NG; ++r)
+#pragma unroll
+    for (int c = 0; c < kCache; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) asm volatile("" : "+v"(cache[r][c][e]));
+#pragma unroll
+  for (int r = 0; r < NG; ++r) {
+    double q = 0.0;
+#pragma unroll
+    for (int c = 0; c < kCache; ++c) {
+      if (c < nc) {
+        const int k0 = (lane + G * c) * E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const double d = (double)cache[r][c][e] - mean[r];
+          q += (k0 + e < l) ? d * d : 0.0;
+        }
+      }
+    }
+    const double m2 = group_sum(q, G);
+    const bool degenerate = !(m2 > 0.0) || !(m2 < INFINITY);
+    inv[r] = degenerate ? (double)NAN : out_scale / sqrt(m2);
+  }
+#pragma unroll
+  for (int r = 0; r < NG; ++r)
+#pragma unroll
+    for (int c = 0; c < kCache; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) asm volatile("" : "+v"(cache[r][c][e]));
+#pragma unroll
+  for (int r = 0; r < NG; ++r) {
+#pragma unroll
+    for (int c = 0; c < kCache; ++c) {
+      if (c < nc) {
+        const int u = lane + G * c;
+        double o[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          o[e] = (u * E + e < l) ? ((double)cache[r][c][e] - mean[r]) * inv[r] : 0.0;
+        if (u < units) store_unit<MODE, E>(zr[r], u, o);
+      }
+    }
+  }
+}
+
 // Zero one padding row of Z (rows n .. n_pad-1).
 __device__ __forceinline__ void zero_row(unsigned char *__restrict__ zr, int64_t row_bytes,
                                          int G = 64) {

@@ -20,6 +20,12 @@ def _datasets(shapes, seed):
     return out
 
 
+def _late_waits(plan):
+    """The kernel's count of bounded waits that expired (the fourth job counter
+    of the plan's workspace); must stay 0."""
+    return int(plan.workspace[384:392].view(__import__("torch").int64).item())
+
+
 @pytest.mark.parametrize("mode", ["split", "fp32"])
 def test_small_batch_vs_single_and_oracle(mode):
     import torch
@@ -31,6 +37,7 @@ def test_small_batch_vs_single_and_oracle(mode):
     plan = pcc.BatchPlan(xs, mode, tiles=tiles)
     plan.launch()
     torch.cuda.synchronize()
+    assert _late_waits(plan) == 0
     for d, X in enumerate(Xs):
         n = X.shape[0]
         got = plan.r[d].cpu().numpy()
@@ -76,6 +83,7 @@ def test_config5_batch_sampled():
         r.fill_(float("nan"))
     plan.launch()
     torch.cuda.synchronize()
+    assert _late_waits(plan) == 0
     total = 0
     for d, (X, pl) in enumerate(batch):
         n = X.shape[0]
