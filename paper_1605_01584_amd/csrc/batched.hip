@@ -104,34 +104,46 @@ __global__ void batch_zero_kernel(unsigned long long *counters) {
 // the batch (FP32/FP64, vector or scalar loads), with the single-matrix
 // kernel's row code and register cache.  A row is owned by `lanes` lanes:
 // short rows share a wave (4 to 32 lanes each), so a wave has several rows'
-// loads in flight at once.  Rows longer than the registers hold (more than
-// 2048 samples) read their remainder from memory again in the later passes
-// (the single-matrix kernel stages it in LDS instead).
+// loads in flight at once.  The part of a row longer than the registers hold
+// (more than 2048 samples) is staged in the wave's share of the tile LDS,
+// which the transformation phase does not use (16 KB per wave: rows of up to
+// 6144 FP32 samples are read from memory once); what remains is read again.
+constexpr int kStageBytesPerWave = 16384;
+static_assert(kStageBytesPerWave * (kTileThreads / 64) <= TileShape<256>::LDS_UNITS * 16,
+              "the waves' staging areas lie inside the tile LDS");
+
 template <typename TIn, int MODE, bool VEC>
 __device__ __forceinline__ void batch_row(const TIn *xr, int64_t l, int64_t l_pad,
-                                          unsigned char *zr, double out_scale, int lanes) {
-  normalize_row<TIn, MODE, CacheOf<TIn, MODE>::C, VEC>(
-      xr, l, l_pad, zr, nullptr, nullptr, out_scale, lanes);
+                                          unsigned char *zr, double out_scale, int lanes,
+                                          unsigned char *stage) {
+  constexpr int E = UnitOf<MODE>::E, kc = CacheOf<TIn, MODE>::C;
+  // only whole-wave rows have units past the registers' share
+  int64_t tail = lanes == 64 ? l_pad / E - 64 * kc : 0;
+  if (tail < 0) tail = 0;
+  constexpr int64_t cap = kStageBytesPerWave / (E * (int64_t)sizeof(TIn));
+  normalize_row<TIn, MODE, kc, VEC>(xr, l, l_pad, zr, nullptr, nullptr, out_scale, lanes,
+                                    reinterpret_cast<TIn *>(stage), (int)(tail < cap ? tail : cap));
 }
 
 // Row `row` (< n) of dataset d, by input type and alignment.
 template <int MODE>
 __device__ __forceinline__ void batch_dataset_row(const BatchDesc &d, int64_t row,
-                                                  unsigned char *zr, int lanes) {
+                                                  unsigned char *zr, int lanes,
+                                                  unsigned char *stage) {
   if (d.xt == PCC_IN_F64) {
     const double *xr = (const double *)d.x + row * d.ldx;
     const bool vec = (d.ldx % 2 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
     if (vec)
-      batch_row<double, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+      batch_row<double, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes, stage);
     else
-      batch_row<double, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+      batch_row<double, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes, stage);
   } else {
     const float *xr = (const float *)d.x + row * d.ldx;
     const bool vec = (d.ldx % 4 == 0) && ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0);
     if (vec)
-      batch_row<float, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+      batch_row<float, MODE, true>(xr, d.l, d.l_pad, zr, d.out_scale, lanes, stage);
     else
-      batch_row<float, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes);
+      batch_row<float, MODE, false>(xr, d.l, d.l_pad, zr, d.out_scale, lanes, stage);
   }
 }
 
@@ -192,7 +204,8 @@ __device__ __forceinline__ bool norm_row_groups_together(const BatchDesc *__rest
 // the descriptor in scalar registers.
 template <int MODE>
 __device__ __forceinline__ void norm_row_group(const BatchDesc *__restrict__ descs,
-                                               const int64_t *keys, int D, int64_t W) {
+                                               const int64_t *keys, int D, int64_t W,
+                                               unsigned char *stage) {
   const BatchDesc &d = descs[__builtin_amdgcn_readfirstlane(find_desc(keys, D, W))];
   const int lanes = d.lanes;
   const int64_t row = (W - d.grp0) * (64 / lanes) + (int64_t)((threadIdx.x & 63) / lanes);
@@ -204,9 +217,9 @@ __device__ __forceinline__ void norm_row_group(const BatchDesc *__restrict__ des
   // a split dataset of short rows holds FP32 z, as the single-matrix
   // transformation writes it
   if (MODE == PCC_SPLIT_BF16X3 && d.l_pad <= kSplitFp32MaxLPad)
-    batch_dataset_row<PCC_FP32>(d, row, zr, lanes);
+    batch_dataset_row<PCC_FP32>(d, row, zr, lanes, stage);
   else
-    batch_dataset_row<MODE>(d, row, zr, lanes);
+    batch_dataset_row<MODE>(d, row, zr, lanes, stage);
 }
 
 // The batch in one persistent kernel: first every workgroup transforms row
@@ -243,6 +256,8 @@ __global__ __launch_bounds__(kTileThreads, 1) void batch_kernel(const BatchDesc 
   if (threadIdx.x == 0) wg_groups = 0u;
   __syncthreads();
   const int64_t *gkeys = load_keys(grp0s, D, skeys);
+  // the wave's share of the tile LDS, for the long rows of phase 1
+  unsigned char *stage = reinterpret_cast<unsigned char *>(smem) + (threadIdx.x >> 6) * kStageBytesPerWave;
   // phase 1: runs of kClaimGroups consecutive row groups, one run per wave
   // at a time (one claim per run keeps the shared counter off the path)
   unsigned int mine = 0u;
@@ -256,7 +271,7 @@ __global__ __launch_bounds__(kTileThreads, 1) void batch_kernel(const BatchDesc 
       if (W + kRowsAtOnce <= W1 && norm_row_groups_together<MODE>(descs, gkeys, D, W)) {
         W += kRowsAtOnce;
       } else {
-        norm_row_group<MODE>(descs, gkeys, D, W);
+        norm_row_group<MODE>(descs, gkeys, D, W, stage);
         ++W;
       }
     }

@@ -50,6 +50,33 @@ def test_small_batch_vs_single_and_oracle(mode):
     plan.close()
 
 
+@pytest.mark.parametrize("mode", ["split", "fp32"])
+def test_long_rows_batch_vs_single_and_oracle(mode):
+    """Rows past the registers' share (2048 samples per wave), partly staged in
+    LDS (up to 6144 FP32 or 4096 FP64 samples) and partly read again: every
+    set bit-identical to the single-set call and within 1e-5 of the oracle."""
+    import torch
+    import paper_1605_01584_amd as pcc
+    shapes = [(300, 4500), (130, 9000), (257, 2049), (70, 6144), (90, 5000)]
+    Xs = _datasets(shapes, 13)          # sets 1 and 4 are FP64
+    xs = [to_device(X) for X in Xs]
+    plan = pcc.BatchPlan(xs, mode, tiles=[256, 128, 0, 128, 256])
+    for r in plan.r:
+        r.fill_(float("nan"))
+    plan.launch()
+    torch.cuda.synchronize()
+    assert _late_waits(plan) == 0
+    for d, X in enumerate(Xs):
+        got = plan.r[d].cpu().numpy()
+        assert np.max(np.abs(got - oracle.pearson_packed(X))) <= 1e-5, d
+        tile = [256, 128, 0, 128, 256][d] or pcc.default_cfg(plan.zd[d]).tile
+        z, zd = pcc.normalize(xs[d], mode)
+        assert torch.equal(plan.z[d], z), d
+        single = pcc.allpairs(z, zd, pcc.TileCfg(tile, 0, 1, 0)).cpu().numpy()
+        assert np.array_equal(got, single), d
+    plan.close()
+
+
 def test_graph_replays_agree():
     import torch
     import paper_1605_01584_amd as pcc
