@@ -287,8 +287,11 @@ pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
  * The second operand (column x) is permuted; Z's mean and norm are
  * invariant under a permutation, so Z is not renormalised.
  * Rows of l_pad <= pcc_permtest_max_l(mode): one persistent launch for all
- * P permutations; jobs are 32 x 32 pair blocks whose two profile panels
- * stay in LDS for all P permutations; `workspace` is unused (may be NULL).
+ * P permutations, with the permuted profiles of a job in LDS for every
+ * sample; `workspace` is unused (may be NULL).  FP32 jobs are 32 x 32 pair
+ * blocks with both profile panels in LDS (l_pad <= 608 on gfx950's 160 KiB);
+ * split jobs are 64 x 32 blocks whose 64 unpermuted profiles are streamed
+ * through LDS (l_pad <= 992).
  * Longer rows: the tiled form of pcc_permtest_tiles with the default
  * schedule; `workspace` must hold pcc_workspace_size(zd, 2) bytes and be
  * 256-byte aligned (NULL or misaligned gives PCC_E_WORKSPACE).
@@ -299,7 +302,7 @@ pcc_status pcc_threshold_edges_xy(const pcc_zdesc *zdx, const void *zx,
  *          checks them.
  *   counts device int32, n(n-1)/2.
  * Supported modes: FP32 (FP32 MFMA; every r within about 1e-7 of exact) and
- * split-BF16x3 (three BF16 products per sample, about 2.7x the FP32 kernel's
+ * split-BF16x3 (three BF16 products per sample, about 3x the FP32 kernel's
  * rate; r within split's 1e-5, so a count can differ from the exact one only
  * in permutations whose |r| lies that close to |r_obs|).  The plain 16-bit
  * modes are refused: their r error (1e-4 and more) would decide too many
@@ -319,7 +322,7 @@ pcc_status pcc_permtest(const pcc_zdesc *zd, const void *z,
  * |r_p| >= |r_obs| to that copy's count slot; the slots are summed at the
  * end.  An identity permutation reproduces r_obs bit for bit, so it counts.
  * counts as for pcc_permtest; the r of a pair is the all-pairs kernel's on
- * this schedule (the LDS kernel rounds in another order, so counts of the
+ * this schedule (the LDS kernels round in another order, so counts of the
  * two forms can differ where some |r_p| lies within rounding of |r_obs|).
  * workspace: device, 256-byte aligned, workspace_bytes >=
  * pcc_workspace_size(zd, 3), else PCC_E_WORKSPACE.  Modes as pcc_permtest. */
@@ -327,8 +330,9 @@ pcc_status pcc_permtest_tiles(const pcc_zdesc *zd, const void *z, const int32_t 
                               int32_t P, int32_t *counts, const pcc_tile_cfg *cfg,
                               void *workspace, size_t workspace_bytes, void *stream);
 
-/* Largest l_pad of the LDS form of pcc_permtest (both 32-profile panels
- * stay in LDS); longer rows take the tiled form.  0 for modes the
+/* Largest l_pad of the LDS form of pcc_permtest (its job's permuted
+ * profiles and, in FP32, the other panel too stay in LDS): 608 in FP32 and
+ * 992 in split on gfx950.  Longer rows take the tiled form.  0 for modes the
  * permutation test does not support. */
 int64_t pcc_permtest_max_l(pcc_mode_t mode);
 

@@ -4,24 +4,21 @@
 // permutation testing, which the evaluation section motivates with at least
 // 1,000 iterations of all-pairs r on permuted data).
 //
-// One persistent launch for all P permutations.  A job is one 32 x 32 block
-// of the pair matrix, placed by the bijection of Eq. (16)-(19) over 32-wide
-// tiles.  Both 32-profile panels stay in LDS for every sample, so a
-// permutation costs no global traffic at all: permuting the column profile
-// is only a different LDS read index, B[k][j] = Z_x[pi(k)] is a ds_read_b32
-// at column j, sample pi(k).  The 16 waves of a workgroup share the job and
-// split the permutations (wave w takes p = w, w + 16, ...), two at a time
-// (two independent accumulators sharing each A read), with no barrier until
-// the job ends; after each pass a wave adds its hits to the job's counts in
-// LDS, which are stored once.
-//
-// Every wave first computes the observed r itself, by the same code path as
-// a permutation with the identity index, so an identity permutation
-// reproduces it bit for bit.  One kernel, two arithmetics by Z's layout: FP32
-// MFMA (v_mfma_f32_32x32x2_f32, r within about 1e-7: the test decides
-// integers from |r| differences) and split-BF16x3 (three
-// v_mfma_f32_32x32x16_bf16 per 16 samples, about 2.7x the FP32 kernel's rate,
-// r within split's 1e-5).
+// One persistent launch for all P permutations, in one of two kernels by
+// Z's layout.  FP32 (v_mfma_f32_32x32x2_f32, r within about 1e-7: the test
+// decides integers from |r| differences): a job is one 32 x 32 block of the
+// pair matrix, placed by the bijection of Eq. (16)-(19) over 32-wide tiles,
+// with both 32-profile panels in LDS for every sample, so a permutation
+// costs no global traffic: permuting the column profile is only a different
+// LDS read index, B[k][j] = Z_x[pi(k)] is a ds_read_b32 at column j, sample
+// pi(k).  The 16 waves of a workgroup share the job and split the
+// permutations two at a time (two accumulators sharing each A read), with no
+// barrier until the job ends; after each pass a wave adds its hits to the
+// job's counts in LDS, which are stored once.  Every wave first computes the
+// observed r itself, by the same code path as a permutation with the
+// identity index, so an identity permutation reproduces it bit for bit.
+// Split-BF16x3 (three v_mfma_f32_32x32x16_bf16 per 16 samples, r within
+// split's 1e-5) uses 64 x 32 jobs, further below.
 #include <algorithm>
 
 #include "pcc_internal.h"
@@ -66,18 +63,13 @@ size_t lds_bytes(int64_t l_pad) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS layouts.  FP32: A rows as stored (pitch l_pad + 4 floats), B rows at
-// pitch l_pad + 1 floats.  Split (per 128-byte chunk of Z the BF16 hi parts
-// of 32 samples, then their lo parts): A rows are the chunks as stored (pitch
-// 4 l_pad + 16 bytes), B rows hold one 32-bit word per sample, hi in the low
-// half and lo in the high half (pitch l_pad + 1 words), so a single
-// ds_read_b32 gather of sample pi(k) brings both BF16 operands of the sample.
-// Both modes store 4 bytes per sample, so both fit the same rows.
+// FP32 LDS layout: A rows as stored (pitch l_pad + 4 floats), B rows at pitch
+// l_pad + 1 floats.
 //
 // Samples k >= l (padding) are zero in A, so whatever finite B value their
 // index selects adds exactly zero: the permutation indices are loaded through
 // a buffer descriptor that spans the row's l entries, and a load past them
-// returns index 0.
+// returns index 0.  (The split kernel relies on the same.)
 //
 // NP permutations per pass share every A read; WAVES waves split the
 // permutations, wave w taking p = w, w + WAVES, ...; slot 0 of a wave's first
@@ -98,75 +90,6 @@ __device__ __forceinline__ void idx_load(__amdgpu_buffer_rsrc_t rs, uint32_t off
 #pragma unroll
     for (int e = 0; e < 8; ++e)
       d[e >> 2][e & 3] = (int)__builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * e, 0, 0);
-  }
-}
-
-// Split step (16 samples) of NP accumulators.  Lane (i, g) takes samples
-// k = 16t + 8g + e, e = 0..7: its A hi and lo operands are one 16-byte unit
-// each (unit 2(t mod 2) + g of chunk t/2, and the unit four further on), its
-// B operands come from 8 gathers, regrouped by v_perm_b32 (the low halves of
-// two words, then their high halves) into a hi and a lo vector; then the
-// three products per accumulator.
-template <int NP, bool IDENT0>
-__device__ __forceinline__ void step_split(const unsigned char *__restrict__ arow,
-                                           const uint32_t *__restrict__ brow, int t, int g,
-                                           const i32x4 (&idx)[NP][2], f32x16 (&acc)[NP]) {
-  const int kb = 16 * t + 8 * g;
-  const unsigned char *ap = arow + (t >> 1) * 128 + ((2 * (t & 1) + g) << 4);
-  const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(ap));
-  const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(ap + 64));
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    uint32_t wd[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      wd[e] = (IDENT0 && j == 0) ? brow[kb + e] : brow[idx[j][e >> 2][e & 3]];
-    u32x4 h, o;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      h[q] = __builtin_amdgcn_perm(wd[2 * q + 1], wd[2 * q], 0x05040100u);
-      o[q] = __builtin_amdgcn_perm(wd[2 * q + 1], wd[2 * q], 0x07060302u);
-    }
-    const bf16x8 bh = __builtin_bit_cast(bf16x8, h);
-    const bf16x8 bl = __builtin_bit_cast(bf16x8, o);
-    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[j], 0, 0, 0);
-    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[j], 0, 0, 0);
-    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[j], 0, 0, 0);
-  }
-}
-
-// One split pass over all samples.  The indices of step t + 1 are loaded
-// before step t runs, into the other of two register sets (steps go in
-// pairs: nt is even), so a step never waits for a load it issued itself.
-template <bool ALIGNED, int NP, bool IDENT0>
-__device__ __forceinline__ void pass_split(const unsigned char *__restrict__ arow,
-                                           const uint32_t *__restrict__ brow,
-                                           const __amdgpu_buffer_rsrc_t (&rs)[NP], int nt, int g,
-                                           f32x16 (&acc)[NP]) {
-#pragma unroll
-  for (int j = 0; j < NP; ++j)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[j][v] = 0.0f;
-  i32x4 even[NP][2], odd[NP][2];
-  const uint32_t o0 = 32 * g;  // byte offset of sample 8g
-#pragma unroll
-  for (int j = 0; j < NP; ++j)
-    if (!(IDENT0 && j == 0)) idx_load<ALIGNED>(rs[j], o0, even[j]);
-  // (scheduling barriers keep each group of loads ahead of the step it
-  // overlaps: the compiler would otherwise sink them next to their use)
-  for (int t = 0; t < nt; t += 2) {
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-      if (!(IDENT0 && j == 0)) idx_load<ALIGNED>(rs[j], o0 + 64 * (t + 1), odd[j]);
-    __builtin_amdgcn_sched_barrier(0);
-    step_split<NP, IDENT0>(arow, brow, t, g, even, acc);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-      if (!(IDENT0 && j == 0)) idx_load<ALIGNED>(rs[j], o0 + 64 * (t + 2), even[j]);
-    __builtin_amdgcn_sched_barrier(0);
-    step_split<NP, IDENT0>(arow, brow, t + 1, g, odd, acc);
-    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -236,8 +159,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t perm_row(const int32_t *perms,
   return __builtin_amdgcn_make_buffer_rsrc((void *)(perms + p * l), (short)0, 4 * l, 0x00020000);
 }
 
-template <int MODE, bool ALIGNED, int NP, int WAVES>
-__global__ __launch_bounds__(64 * WAVES, 1) void permtest_mfma_kernel(
+template <bool ALIGNED, int NP, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 1) void permtest_f32_kernel(
     const unsigned char *__restrict__ z, int64_t row_bytes, int64_t n, int64_t l, int64_t l_pad,
     int64_t mb, const int32_t *__restrict__ perms, int32_t P, int32_t *__restrict__ counts) {
   constexpr int kT = 64 * WAVES;
@@ -252,12 +175,10 @@ __global__ __launch_bounds__(64 * WAVES, 1) void permtest_mfma_kernel(
   // the wave index in an SGPR: permutation rows are then scalar base addresses
   const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i = lane & 31, g = lane >> 5;
-  constexpr bool kSplit = MODE == PCC_SPLIT_BF16X3;
-  const int nt = (int)(l_pad / (kSplit ? 16 : 8));
+  const int nt = (int)(l_pad / 8);
   const int64_t njobs = mb * (mb + 1) / 2;
   const int64_t G = gridDim.x;
   const int64_t u4 = l_pad / 4;   // 16-byte units per row
-  const int64_t g8 = l_pad / 8;   // groups of 8 samples per row
 
   for (int64_t J = xcd_slot(blockIdx.x, G); J < njobs; J += G) {
     const Cell cell = tri_cell(mb, J);
@@ -268,27 +189,11 @@ __global__ __launch_bounds__(64 * WAVES, 1) void permtest_mfma_kernel(
       *reinterpret_cast<u32x4 *>(sA + r * pa + 16 * u) =
           *reinterpret_cast<const u32x4 *>(z + (y0 + r) * row_bytes + 16 * u);
     }
-    if constexpr (kSplit) {
-      for (int64_t q = tid; q < kBlk * g8; q += kT) {
-        // samples 32c + 8s .. + 7: hi in unit s of chunk c, lo in unit s + 4
-        const int64_t r = q / g8, c = (q % g8) >> 2, s = q & 3;
-        const unsigned char *src = z + (x0 + r) * row_bytes + c * 128 + 16 * s;
-        const u32x4 hv = *reinterpret_cast<const u32x4 *>(src);
-        const u32x4 lv = *reinterpret_cast<const u32x4 *>(src + 64);
-        uint32_t *d = sB + r * pb + 32 * c + 8 * s;
-#pragma unroll
-        for (int q2 = 0; q2 < 4; ++q2) {
-          d[2 * q2] = (hv[q2] & 0xffffu) | (lv[q2] << 16);
-          d[2 * q2 + 1] = (hv[q2] >> 16) | (lv[q2] & 0xffff0000u);
-        }
-      }
-    } else {
-      for (int64_t q = tid; q < kBlk * u4; q += kT) {
-        const int64_t r = q / u4, u = q % u4;
-        const u32x4 v = *reinterpret_cast<const u32x4 *>(z + (x0 + r) * row_bytes + 16 * u);
-        uint32_t *d = sB + r * pb + 4 * u;
-        d[0] = v[0]; d[1] = v[1]; d[2] = v[2]; d[3] = v[3];
-      }
+    for (int64_t q = tid; q < kBlk * u4; q += kT) {
+      const int64_t r = q / u4, u = q % u4;
+      const u32x4 v = *reinterpret_cast<const u32x4 *>(z + (x0 + r) * row_bytes + 16 * u);
+      uint32_t *d = sB + r * pb + 4 * u;
+      d[0] = v[0]; d[1] = v[1]; d[2] = v[2]; d[3] = v[3];
     }
     for (int q = tid; q < kBlk * kBlk; q += kT) sC[q] = 0;
     __syncthreads();
@@ -310,11 +215,8 @@ __global__ __launch_bounds__(64 * WAVES, 1) void permtest_mfma_kernel(
           const int64_t p = w + (int64_t)WAVES * (j - 1);
           rs[j] = perm_row(perms, j > 0 && p < P ? p : w, (int)l);
         }
-        if constexpr (kSplit)
-          pass_split<ALIGNED, NP, true>(arow, brow, rs, nt, g, acc);
-        else
-          pass_f32<ALIGNED, NP, true>(reinterpret_cast<const float *>(arow),
-                                      reinterpret_cast<const float *>(brow), rs, nt, g, acc);
+        pass_f32<ALIGNED, NP, true>(reinterpret_cast<const float *>(arow),
+                                    reinterpret_cast<const float *>(brow), rs, nt, g, acc);
 #pragma unroll
         for (int v = 0; v < 16; ++v) robs[v] = fabsf(clamp_unit(acc[0][v]));
 #pragma unroll
@@ -334,11 +236,8 @@ __global__ __launch_bounds__(64 * WAVES, 1) void permtest_mfma_kernel(
           const int64_t p = p0 + (int64_t)WAVES * j;
           rs[j] = perm_row(perms, p < P ? p : p0, (int)l);
         }
-        if constexpr (kSplit)
-          pass_split<ALIGNED, NP, false>(arow, brow, rs, nt, g, acc);
-        else
-          pass_f32<ALIGNED, NP, false>(reinterpret_cast<const float *>(arow),
-                                       reinterpret_cast<const float *>(brow), rs, nt, g, acc);
+        pass_f32<ALIGNED, NP, false>(reinterpret_cast<const float *>(arow),
+                                     reinterpret_cast<const float *>(brow), rs, nt, g, acc);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           int c = 0;
@@ -355,15 +254,266 @@ __global__ __launch_bounds__(64 * WAVES, 1) void permtest_mfma_kernel(
       const int64_t y = y0 + r, x = x0 + c;
       if (y < x && x < n) {
         // degenerate profiles are NaN rows of Z; sample 0 shows it
-        bool nan;
-        if constexpr (kSplit) {
-          nan = bf16_is_nan(*reinterpret_cast<const uint16_t *>(sA + r * pa)) ||
-                bf16_is_nan(sB[c * pb] & 0xffffu);
-        } else {
-          const float a0 = *reinterpret_cast<const float *>(sA + r * pa);
-          const float b0 = __builtin_bit_cast(float, sB[c * pb]);
-          nan = !(a0 == a0) || !(b0 == b0);
+        const float a0 = *reinterpret_cast<const float *>(sA + r * pa);
+        const float b0 = __builtin_bit_cast(float, sB[c * pb]);
+        const bool nan = !(a0 == a0) || !(b0 == b0);
+        counts[packed_index(n, y, x)] = nan ? -1 : sC[q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split-BF16x3 permutation test on 64 x 32 jobs.  B rows hold one 32-bit
+// word per sample, hi in the low half and lo in the high half, so a single
+// ds_read_b32 gather of sample pi(k) brings both BF16 operands of the
+// sample; per 16 samples and slot, 8 gathers are regrouped by v_perm_b32
+// into a hi and a lo operand vector.  On 32 x 32 jobs (the FP32 kernel's
+// shape) each gathered word would feed one 32-row MFMA block, and at three
+// BF16 MFMAs per 16 samples the gathers and the regrouping would weigh as
+// much as the MFMAs.  Here a job is 64 rows by 32 columns (the two column
+// halves of a 64-wide tile of the inclusive triangle, Eq. (16)-(19)), so
+// every gathered word and its regrouping feed two 32-row blocks.  The 32 permuted column
+// profiles stay in LDS for every sample as before; the 64 sequential
+// profiles are streamed through a ring of two segments of CS 32-sample
+// chunks instead (a 64-row panel would not fit beside them), and all waves
+// walk the samples in step: one barrier per segment, the next segment's copy
+// in flight meanwhile.  Longer segments mean fewer barriers, so the launcher
+// takes the longest that divides the row's chunks and fits the LDS beside
+// the rows.
+// A pass gives every wave NP slots; slot s of the job is the identity for
+// s = 0 (the observed r, which wave 0 writes to LDS after the first pass)
+// and permutation s - 1 after it.  The identity slot gathers through a
+// table of indices 0, 1, 2, ..., so it runs the code of every other slot and
+// an identity permutation reproduces the observed r bit for bit.
+constexpr int kRows2 = 64;  // sequential profiles per job
+constexpr int kIotaLen = 1024;
+
+// A staged chunk holds 32 samples of the 64 rows, 144 bytes a row: the
+// 128-byte chunk and one 16-byte unit of padding (9 units, an odd number, so
+// the ds_read_b128 of 8 consecutive rows hit distinct bank groups).
+constexpr int kChunkPitch = 144;
+constexpr int kChunkBytes = kRows2 * kChunkPitch;
+
+struct IotaTable {
+  int32_t v[kIotaLen];
+  constexpr IotaTable() : v() {
+    for (int k = 0; k < kIotaLen; ++k) v[k] = k;
+  }
+};
+__device__ const IotaTable kIota;
+
+size_t lds_bytes_split64(int64_t l_pad, int cs) {
+  const size_t b = ((size_t)kBlk * pitch_b(l_pad) * 4 + 15) / 16 * 16;
+  return b + 2 * (size_t)cs * kChunkBytes + 2 * (size_t)kRows2 * kBlk * 4;
+}
+
+// One 16-sample step of NP slots on both 32-row blocks: per slot 8 gathers
+// and 8 regroupings feed six MFMAs.  Every slot's gathers are issued before
+// the first MFMA, so the later slots' LDS latency hides behind the earlier
+// slots' MFMAs.  `ring` points at the step's staged chunk, rows kPitch bytes
+// apart.
+template <int NP, int kPitch>
+__device__ __forceinline__ void step_split64(const unsigned char *__restrict__ ring,
+                                             const uint32_t *__restrict__ brow, int t, int i,
+                                             int g, const i32x4 (&idx)[NP][2],
+                                             f32x16 (&acc)[NP][2]) {
+  const unsigned char *ap = ring + i * kPitch + ((2 * (t & 1) + g) << 4);
+  bf16x8 ah[2], al[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    ah[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(ap + b * 32 * kPitch));
+    al[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(ap + b * 32 * kPitch + 64));
+  }
+  uint32_t wd[NP][8];
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) wd[j][e] = brow[idx[j][e >> 2][e & 3]];
+  // (the scheduler would otherwise sink the later slots' gathers below the
+  // first slot's MFMAs)
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    u32x4 h, o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      h[q] = __builtin_amdgcn_perm(wd[j][2 * q + 1], wd[j][2 * q], 0x05040100u);
+      o[q] = __builtin_amdgcn_perm(wd[j][2 * q + 1], wd[j][2 * q], 0x07060302u);
+    }
+    const bf16x8 bh = __builtin_bit_cast(bf16x8, h);
+    const bf16x8 bl = __builtin_bit_cast(bf16x8, o);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc[j][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[b], bh, acc[j][b], 0, 0, 0);
+      acc[j][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[b], bl, acc[j][b], 0, 0, 0);
+      acc[j][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[b], bh, acc[j][b], 0, 0, 0);
+    }
+  }
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Copy chunk c of the job's 64 sequential rows (descriptor rz over those
+// rows) into a staged chunk (64 rows of kChunkPitch bytes) by buffer-to-LDS
+// DMA.  A DMA instruction fills 64 consecutive 16-byte LDS units; the staged
+// chunk is 64 rows of 9 units (the last one padding), so instruction q fills
+// linear units 64 q .. 64 q + 63, lane L the unit (row, slot) =
+// divmod(64 q + L, 9), and a padding slot takes a copy of the row's first
+// unit.  Wave w issues instruction w when w < 9.
+__device__ __forceinline__ void chunk_dma(__amdgpu_buffer_rsrc_t rz, unsigned char *dst, int c,
+                                          uint32_t row_bytes, int w, int lane) {
+  constexpr int kUPR = kChunkPitch / 16;  // 9 units per staged row
+  if (w < kUPR) {
+    const uint32_t m = (uint32_t)(64 * w + lane);
+    const uint32_t r = m / kUPR, v0 = m % kUPR;
+    const uint32_t v = v0 < 8u ? v0 : 0u;
+    const uint32_t voff = r * row_bytes + (uint32_t)c * 128u + 16u * v;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rz, (lds_void *)(dst + w * 1024), 16, voff, 0, 0, 0);
+  }
+}
+
+template <bool ALIGNED, int W, int NP, int CS>
+__global__ __launch_bounds__(64 * W, 1) void permtest_split64_kernel(
+    const unsigned char *__restrict__ z, int64_t row_bytes, int64_t n, int64_t l, int64_t l_pad,
+    int64_t mb, const int32_t *__restrict__ perms, int32_t P, int32_t *__restrict__ counts) {
+  constexpr int kT = 64 * W;
+  constexpr int kSlots = W * NP;  // slots per pass
+  constexpr int kSegBytes = CS * kChunkBytes;  // one ring half
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int64_t pb = pitch_b(l_pad);  // words
+  // observed |r| and counts first (small LDS offsets), then the ring, then
+  // the permuted rows
+  float *sRobs = reinterpret_cast<float *>(dyn);
+  int32_t *sC = reinterpret_cast<int32_t *>(sRobs + kRows2 * kBlk);
+  unsigned char *sRing = reinterpret_cast<unsigned char *>(sC + kRows2 * kBlk);
+  uint32_t *sB = reinterpret_cast<uint32_t *>(sRing + 2 * kSegBytes);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i = lane & 31, g = lane >> 5;
+  const int nc = (int)(l_pad / 32);  // chunks per row
+  const int64_t njobs = mb * (mb + 1);  // two column halves per tile
+  const int64_t G = gridDim.x;
+  const int64_t g8 = l_pad / 8;
+  const int npass = (P + kSlots) / kSlots;  // P + 1 slots, slot 0 the identity
+  const uint32_t o0 = 32 * g;               // byte offset of sample 8g in an index row
+
+  for (int64_t J = xcd_slot(blockIdx.x, G); J < njobs; J += G) {
+    const Cell cell = tri_cell(mb, J >> 1);
+    const int64_t y0 = cell.y * kRows2, x0 = cell.x * kRows2 + kBlk * (J & 1);
+    if (x0 >= n) continue;  // the right half of a tile past the last profile
+    __syncthreads();        // the previous job is done with the LDS
+    for (int64_t q = tid; q < kBlk * g8; q += kT) {
+      // samples 32c + 8s .. + 7: hi in unit s of chunk c, lo in unit s + 4
+      const int64_t r = q / g8, c = (q % g8) >> 2, s = q & 3;
+      const unsigned char *src = z + (x0 + r) * row_bytes + c * 128 + 16 * s;
+      const u32x4 hv = *reinterpret_cast<const u32x4 *>(src);
+      const u32x4 lv = *reinterpret_cast<const u32x4 *>(src + 64);
+      uint32_t *d = sB + r * pb + 32 * c + 8 * s;
+#pragma unroll
+      for (int q2 = 0; q2 < 4; ++q2) {
+        d[2 * q2] = (hv[q2] & 0xffffu) | (lv[q2] << 16);
+        d[2 * q2 + 1] = (hv[q2] >> 16) | (lv[q2] & 0xffff0000u);
+      }
+    }
+    for (int q = tid; q < kRows2 * kBlk; q += kT) sC[q] = 0;
+    const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(z + y0 * row_bytes), (short)0, (int)(kRows2 * row_bytes), 0x00020000);
+#pragma unroll
+    for (int h = 0; h < CS; ++h) chunk_dma(rz, sRing + h * kChunkBytes, h, (uint32_t)row_bytes, w, lane);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+
+    const uint32_t *brow = sB + (int64_t)i * pb;
+    int seq = 0;  // segments consumed in this job; the ring half is seq & 1
+    for (int pass = 0; pass < npass; ++pass) {
+      const int s0 = (pass * W + w) * NP;  // this wave's first slot
+      const bool active = s0 <= P;
+      __amdgpu_buffer_rsrc_t rs[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        // a slot past P repeats the wave's first slot and is not counted (an
+        // inactive wave loads nothing, its descriptors only stay in range)
+        const int s = (s0 + j <= P) ? s0 + j : (s0 <= P ? s0 : 0);
+        rs[j] = s == 0 ? perm_row(kIota.v, 0, (int)l) : perm_row(perms, s - 1, (int)l);
+      }
+      f32x16 acc[NP][2];
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[j][b][v] = 0.0f;
+      i32x4 even[NP][2], odd[NP][2];
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) idx_load<ALIGNED>(rs[j], o0, even[j]);
+      }
+#pragma unroll 1
+      for (int c = 0; c < nc; ++c) {
+        // chunk h of the current segment is read from the ring half seq & 1
+        // while chunk h of the next segment (CS chunks on, wrapping into the
+        // next pass) is copied into the other half
+        const int h = c % CS;
+        const int cn = c + CS >= nc ? c + CS - nc : c + CS;
+        chunk_dma(rz, sRing + ((seq + 1) & 1) * kSegBytes + h * kChunkBytes, cn,
+                  (uint32_t)row_bytes, w, lane);
+        const unsigned char *ring = sRing + (seq & 1) * kSegBytes + h * kChunkBytes;
+        if (active) {
+          const int t = 2 * c;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) idx_load<ALIGNED>(rs[j], o0 + 64 * (t + 1), odd[j]);
+          __builtin_amdgcn_sched_barrier(0);
+          step_split64<NP, kChunkPitch>(ring, brow, t, i, g, even, acc);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int j = 0; j < NP; ++j) idx_load<ALIGNED>(rs[j], o0 + 64 * (t + 2), even[j]);
+          __builtin_amdgcn_sched_barrier(0);
+          step_split64<NP, kChunkPitch>(ring, brow, t + 1, i, g, odd, acc);
+          __builtin_amdgcn_sched_barrier(0);
         }
+        if (h == CS - 1) {
+          asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's copies landed
+          __syncthreads();
+          ++seq;
+        }
+      }
+      if (pass == 0) {
+        // slot 0 of wave 0 is the observed r
+        if (w == 0) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+              sRobs[(32 * b + 8 * (v >> 2) + 4 * g + (v & 3)) * kBlk + i] =
+                  fabsf(clamp_unit(acc[0][b][v]));
+        }
+        __syncthreads();
+      }
+      if (active) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int q = (32 * b + 8 * (v >> 2) + 4 * g + (v & 3)) * kBlk + i;
+            const float ro = sRobs[q];
+            int cnt = 0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j)
+              if (s0 + j >= 1 && s0 + j <= P) cnt += (fabsf(clamp_unit(acc[j][b][v])) >= ro) ? 1 : 0;
+            atomicAdd(sC + q, cnt);
+          }
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < kRows2 * kBlk; q += kT) {
+      const int r = q / kBlk, c = q % kBlk;
+      const int64_t y = y0 + r, x = x0 + c;
+      if (y < x && x < n) {
+        // degenerate profiles are NaN rows of Z; sample 0 shows it
+        const bool nan = bf16_is_nan(*reinterpret_cast<const uint16_t *>(z + y * row_bytes)) ||
+                         bf16_is_nan(sB[c * pb] & 0xffffu);
         counts[packed_index(n, y, x)] = nan ? -1 : sC[q];
       }
     }
@@ -671,36 +821,56 @@ hipError_t launch_permtest_tiles(const pcc_zdesc &zd, const void *z, const int32
 
 int64_t permtest_max_l(int mode) {
   if (mode != PCC_FP32 && mode != PCC_SPLIT_BF16X3) return 0;
-  // largest multiple of 32 whose LDS footprint fits one workgroup (both
-  // modes store 4 bytes per sample)
+  // largest multiple of 32 whose LDS footprint fits one workgroup
   const int64_t cap = max_lds_per_block();
   int64_t lp = 0;
-  while (lds_bytes(lp + 32) <= (size_t)cap) lp += 32;
+  if (mode == PCC_SPLIT_BF16X3) {
+    while (lp + 32 <= kIotaLen && lds_bytes_split64(lp + 32, 1) <= (size_t)cap) lp += 32;
+  } else {
+    while (lds_bytes(lp + 32) <= (size_t)cap) lp += 32;
+  }
   return lp;
 }
 
-// Kernel shapes: permutations per pass and waves per workgroup.
+// Kernel shapes: waves per workgroup and permutations per wave and pass; the
+// split kernel's longest segment (chunks per barrier).
+constexpr int kSplitWaves = 12;
 constexpr int kSplitNP = 2;
-constexpr int kSplitWaves = 16;
+constexpr int kSplitMaxCS = 4;
 constexpr int kF32NP = 2;
 constexpr int kF32Waves = 16;
 
+template <int CS>
+const void *split64_kernel(bool aligned) {
+  return aligned ? (const void *)permtest_split64_kernel<true, kSplitWaves, kSplitNP, CS>
+                 : (const void *)permtest_split64_kernel<false, kSplitWaves, kSplitNP, CS>;
+}
+
 hipError_t launch_permtest(const pcc_zdesc &zd, const void *z, const int32_t *perms, int32_t P,
                            int32_t *counts, int cus, hipStream_t st) {
-  const int64_t mb = (zd.n + kBlk - 1) / kBlk;
-  const int64_t jobs = mb * (mb + 1) / 2;
-  const size_t lds = lds_bytes(zd.l_pad);
   const bool aligned = (zd.l % 4) == 0 && ((reinterpret_cast<uintptr_t>(perms) & 15) == 0);
   const bool split = arith_mode(zd) == PCC_SPLIT_BF16X3;
+  // split: 64-wide tiles, two jobs each; FP32: 32 x 32 jobs
+  const int64_t mb = split ? (zd.n + kRows2 - 1) / kRows2 : (zd.n + kBlk - 1) / kBlk;
+  const int64_t jobs = split ? mb * (mb + 1) : mb * (mb + 1) / 2;
+  size_t lds;
   const void *k;
   int threads;
   if (split) {
-    k = aligned ? (const void *)permtest_mfma_kernel<PCC_SPLIT_BF16X3, true, kSplitNP, kSplitWaves>
-                : (const void *)permtest_mfma_kernel<PCC_SPLIT_BF16X3, false, kSplitNP, kSplitWaves>;
+    // the longest segment whose ring fits beside the rows
+    const size_t cap = (size_t)max_lds_per_block();
+    const int64_t nc = zd.l_pad / 32;
+    int cs = kSplitMaxCS;
+    while (cs > 1 && (nc % cs != 0 || lds_bytes_split64(zd.l_pad, cs) > cap)) --cs;
+    lds = lds_bytes_split64(zd.l_pad, cs);
+    k = cs >= 4 ? split64_kernel<4>(aligned)
+        : cs == 3 ? split64_kernel<3>(aligned)
+        : cs == 2 ? split64_kernel<2>(aligned) : split64_kernel<1>(aligned);
     threads = 64 * kSplitWaves;
   } else {
-    k = aligned ? (const void *)permtest_mfma_kernel<PCC_FP32, true, kF32NP, kF32Waves>
-                : (const void *)permtest_mfma_kernel<PCC_FP32, false, kF32NP, kF32Waves>;
+    lds = lds_bytes(zd.l_pad);
+    k = aligned ? (const void *)permtest_f32_kernel<true, kF32NP, kF32Waves>
+                : (const void *)permtest_f32_kernel<false, kF32NP, kF32Waves>;
     threads = 64 * kF32Waves;
   }
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -192,12 +192,25 @@ def test_default_cfg():
 
 def test_permtest_limit_is_lds_bound():
     import paper_1605_01584_amd as pcc
-    # without a device the library assumes gfx950's 160 KiB per workgroup; with
-    # one it uses the device's limit.  Either way a positive multiple of 32.
-    lim = pcc.permtest_max_l("fp32")
-    assert lim > 0 and lim % 32 == 0
-    # split stores 4 bytes per sample too: the same limit
-    assert pcc.permtest_max_l("split") == lim
+    # without a device the library assumes gfx950's 160 KiB per workgroup (with
+    # one it uses the device's limit): the largest multiple of 32 whose LDS
+    # footprint fits.  FP32 holds two 32-row panels (rows padded by 16 and 4
+    # bytes) and 32 x 32 counts; split holds the 32 permuted rows, a ring of
+    # two 64-row chunks at 144 bytes a row, and 64 x 32 observed |r| and
+    # counts, and its identity table caps it at 1024 samples.
+    cap = 160 * 1024
+
+    def fp32_bytes(lp):
+        return 32 * (lp + 4) * 4 + (32 * (lp + 1) * 4 + 15) // 16 * 16 + 32 * 32 * 4
+
+    def split_bytes(lp):
+        return (32 * (lp + 1) * 4 + 15) // 16 * 16 + 2 * 64 * 144 + 2 * 64 * 32 * 4
+
+    def largest(f, top):
+        return max(lp for lp in range(32, top + 1, 32) if f(lp) <= cap)
+
+    assert pcc.permtest_max_l("fp32") == largest(fp32_bytes, 4096) == 608
+    assert pcc.permtest_max_l("split") == largest(split_bytes, 1024) == 992
     assert pcc.permtest_max_l("bf16") == 0 and pcc.permtest_max_l("fp16") == 0
     assert pcc.permtest_max_l("fp64") == 0
 

@@ -56,17 +56,19 @@ def _check(got, X, perms, I, J, mode):
 @pytest.mark.parametrize("n,l,P", [(200, 5000, 24), (300, 609, 25), (257, 1000, 33),
                                    (130, 2049, 7), (2, 700, 5), (50, 20000, 4), (40, 33000, 3)])
 def test_long_rows_all_pairs(mode, n, l, P):
-    """Rows past the LDS kernel's limit, through pcc_permtest (which takes the
-    tiled form for them) on every pair.  The gather of permuted copies stages
-    8 rows in LDS up to 4096 samples, one row up to 32768 samples, and reads
-    longer rows from memory (l = 33000)."""
+    """Long rows on every pair: through pcc_permtest where the rows are past
+    the LDS kernel's limit (it takes the tiled form for them), through
+    pcc_permtest_tiles where that kernel would still hold them (the split
+    kernel holds rows of up to 992 samples, the FP32 one up to 608).  The
+    gather of permuted copies stages 8 rows in LDS up to 4096 samples, one
+    row up to 32768 samples, and reads longer rows from memory (l = 33000)."""
     import paper_1605_01584_amd as pcc
     zd = pcc.z_layout(n, l, mode)
-    assert zd.l_pad > pcc.permtest_max_l(mode)
+    direct = zd.l_pad <= pcc.permtest_max_l(mode)
     X, _ = workloads.planted(n, l, n + l, n_planted=min(5, n // 2), dtype=np.float32)
     perms = _perms(l, P, n * 7 + l)
-    print(f"[permtest tiles] {mode} n={n} l={l} P={P}", flush=True)
-    got = _gpu(X, perms, mode, tiles=False)
+    print(f"[permtest tiles] {mode} n={n} l={l} P={P} direct={direct}", flush=True)
+    got = _gpu(X, perms, mode, tiles=direct)
     I, J = np.triu_indices(n, 1)
     loose = _check(got, X, perms, I, J, mode)
     assert np.all((got >= 0) & (got <= P))
