@@ -360,16 +360,21 @@ typedef __attribute__((address_space(3))) void lds_void;
 // chunk is 64 rows of 9 units (the last one padding), so instruction q fills
 // linear units 64 q .. 64 q + 63, lane L the unit (row, slot) =
 // divmod(64 q + L, 9), and a padding slot takes a copy of the row's first
-// unit.  Wave w issues instruction w when w < 9.
+// unit.  Wave w issues instructions w, w + W, ...
+template <int W>
 __device__ __forceinline__ void chunk_dma(__amdgpu_buffer_rsrc_t rz, unsigned char *dst, int c,
                                           uint32_t row_bytes, int w, int lane) {
-  constexpr int kUPR = kChunkPitch / 16;  // 9 units per staged row
-  if (w < kUPR) {
-    const uint32_t m = (uint32_t)(64 * w + lane);
-    const uint32_t r = m / kUPR, v0 = m % kUPR;
-    const uint32_t v = v0 < 8u ? v0 : 0u;
-    const uint32_t voff = r * row_bytes + (uint32_t)c * 128u + 16u * v;
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rz, (lds_void *)(dst + w * 1024), 16, voff, 0, 0, 0);
+  constexpr int kUPR = kChunkPitch / 16;  // 9 units per staged row, 9 instructions
+#pragma unroll
+  for (int k = 0; k < (kUPR + W - 1) / W; ++k) {
+    const int q = w + k * W;
+    if (q < kUPR) {
+      const uint32_t m = (uint32_t)(64 * q + lane);
+      const uint32_t r = m / kUPR, v0 = m % kUPR;
+      const uint32_t v = v0 < 8u ? v0 : 0u;
+      const uint32_t voff = r * row_bytes + (uint32_t)c * 128u + 16u * v;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rz, (lds_void *)(dst + q * 1024), 16, voff, 0, 0, 0);
+    }
   }
 }
 
@@ -421,7 +426,7 @@ __global__ __launch_bounds__(64 * W, 1) void permtest_split64_kernel(
     const __amdgpu_buffer_rsrc_t rz = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(z + y0 * row_bytes), (short)0, (int)(kRows2 * row_bytes), 0x00020000);
 #pragma unroll
-    for (int h = 0; h < CS; ++h) chunk_dma(rz, sRing + h * kChunkBytes, h, (uint32_t)row_bytes, w, lane);
+    for (int h = 0; h < CS; ++h) chunk_dma<W>(rz, sRing + h * kChunkBytes, h, (uint32_t)row_bytes, w, lane);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(64 * W, 1) void permtest_split64_kernel(
         // next pass) is copied into the other half
         const int h = c % CS;
         const int cn = c + CS >= nc ? c + CS - nc : c + CS;
-        chunk_dma(rz, sRing + ((seq + 1) & 1) * kSegBytes + h * kChunkBytes, cn,
+        chunk_dma<W>(rz, sRing + ((seq + 1) & 1) * kSegBytes + h * kChunkBytes, cn,
                   (uint32_t)row_bytes, w, lane);
         const unsigned char *ring = sRing + (seq & 1) * kSegBytes + h * kChunkBytes;
         if (active) {
