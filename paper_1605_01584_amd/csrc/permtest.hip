@@ -273,20 +273,20 @@ __global__ __launch_bounds__(64 * WAVES, 1) void permtest_f32_kernel(
 // BF16 MFMAs per 16 samples the gathers and the regrouping would weigh as
 // much as the MFMAs.  Here a job is 64 rows by 32 columns (the two column
 // halves of a 64-wide tile of the inclusive triangle, Eq. (16)-(19)), so
-// every gathered word and its regrouping feed two 32-row blocks.  The 32 permuted column
-// profiles stay in LDS for every sample as before; the 64 sequential
-// profiles are streamed through a ring of two segments of CS 32-sample
-// chunks instead (a 64-row panel would not fit beside them), and all waves
-// walk the samples in step: one barrier per segment, the next segment's copy
-// in flight meanwhile.  Longer segments mean fewer barriers, so the launcher
-// takes the longest that divides the row's chunks and fits the LDS beside
-// the rows.
+// every gathered word and its regrouping feed two 32-row blocks.  The 32
+// permuted profiles stay in LDS for every sample, as in the FP32 kernel; the
+// 64 unpermuted profiles are streamed through a ring of two segments of CS
+// 32-sample chunks instead (a 64-row panel would not fit beside them), and
+// all waves walk the samples in step: one barrier per segment, the next
+// segment's copy in flight meanwhile.  Longer segments mean fewer barriers,
+// so the launcher takes the longest that divides the row's chunks and fits
+// the LDS beside the rows.
 // A pass gives every wave NP slots; slot s of the job is the identity for
 // s = 0 (the observed r, which wave 0 writes to LDS after the first pass)
 // and permutation s - 1 after it.  The identity slot gathers through a
 // table of indices 0, 1, 2, ..., so it runs the code of every other slot and
 // an identity permutation reproduces the observed r bit for bit.
-constexpr int kRows2 = 64;  // sequential profiles per job
+constexpr int kRows2 = 64;  // unpermuted profiles per job
 constexpr int kIotaLen = 1024;
 
 // A staged chunk holds 32 samples of the 64 rows, 144 bytes a row: the
@@ -354,7 +354,7 @@ __device__ __forceinline__ void step_split64(const unsigned char *__restrict__ r
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// Copy chunk c of the job's 64 sequential rows (descriptor rz over those
+// Copy chunk c of the job's 64 unpermuted rows (descriptor rz over those
 // rows) into a staged chunk (64 rows of kChunkPitch bytes) by buffer-to-LDS
 // DMA.  A DMA instruction fills 64 consecutive 16-byte LDS units; the staged
 // chunk is 64 rows of 9 units (the last one padding), so instruction q fills
