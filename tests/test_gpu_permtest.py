@@ -90,9 +90,16 @@ def test_longest_rows(mode):
 
 
 @pytest.mark.parametrize("mode", ["fp32", "split"])
-def test_identity_and_repeated_permutations(mode):
+@pytest.mark.parametrize("l", [64, 160, 512])
+def test_identity_and_repeated_permutations(mode, l):
+    """An identity permutation reproduces the observed r bit for bit, so it
+    always counts; P copies of one permutation give 0 or P.  (Split rows of
+    at most 64 samples are computed in FP32; l = 160 and 512 run the split
+    kernel, whose observed r goes through an identity index table.  P = 50
+    spreads the slots over three passes of the split kernel and two of the
+    FP32 one.)"""
     rng = np.random.default_rng(1)
-    n, l, P = 290, 64, 9
+    n, P = 290, 50
     X = rng.standard_normal((n, l)).astype(np.float32)
     ident = np.tile(np.arange(l, dtype=np.int32), (P, 1))
     assert np.all(_gpu_counts(X, ident, mode) == P)
@@ -102,9 +109,10 @@ def test_identity_and_repeated_permutations(mode):
 
 
 @pytest.mark.parametrize("mode", ["fp32", "split"])
-def test_zero_permutations_and_degenerate_rows(mode):
+@pytest.mark.parametrize("l", [20, 100])
+def test_zero_permutations_and_degenerate_rows(mode, l):
     rng = np.random.default_rng(2)
-    n, l = 100, 20
+    n = 100
     X = rng.standard_normal((n, l)).astype(np.float32)
     X[3] = 0.5
     perms = np.stack([rng.permutation(l) for _ in range(4)]).astype(np.int32)
