@@ -554,7 +554,9 @@ int64_t max_lds_per_block() {
 // sample order; a split row is 128-byte chunks of 32 BF16 hi values and the
 // 32 matching lo values.
 //
-// A workgroup takes R rows and every copy of the launch.  The R rows are
+// A workgroup of 16 waves takes R rows and every copy of the launch (with
+// only 128 KB of LDS free for one workgroup per compute unit, 16 waves keep
+// more of the gather's memory accesses in flight than 4).  The R rows are
 // first staged in LDS as one 32-bit word per sample (the FP32 value, or the
 // sample's hi in the low half and lo in the high half), so every gathered
 // sample is one LDS read and each row is read from memory once per launch;
@@ -562,7 +564,7 @@ int64_t max_lds_per_block() {
 // units of the copies: 4 samples (FP32), or the hi unit and lo unit of 8
 // samples (split).
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void perm_gather_lds_kernel(
+__global__ __launch_bounds__(1024) void perm_gather_lds_kernel(
     const unsigned char *__restrict__ z, int64_t row_bytes, int64_t n_pad, int64_t l,
     int64_t l_pad, int R, const int32_t *__restrict__ perms, int64_t p0, int copies,
     unsigned char *__restrict__ zp, int64_t zp_stride) {
@@ -795,11 +797,11 @@ hipError_t launch_permtest_tiles(const pcc_zdesc &zd, const void *z, const int32
       const size_t lds = (size_t)R * (size_t)row_lds;
       const unsigned blocks = (unsigned)((zd.n_pad + R - 1) / R);
       if (split)
-        hipLaunchKernelGGL(perm_gather_lds_kernel<true>, dim3(blocks), dim3(256), lds, st,
+        hipLaunchKernelGGL(perm_gather_lds_kernel<true>, dim3(blocks), dim3(1024), lds, st,
                            (const unsigned char *)z, zd.row_bytes, zd.n_pad, zd.l, zd.l_pad, R,
                            perms, p0, (int)sc, w.zp, zd.bytes);
       else
-        hipLaunchKernelGGL(perm_gather_lds_kernel<false>, dim3(blocks), dim3(256), lds, st,
+        hipLaunchKernelGGL(perm_gather_lds_kernel<false>, dim3(blocks), dim3(1024), lds, st,
                            (const unsigned char *)z, zd.row_bytes, zd.n_pad, zd.l, zd.l_pad, R,
                            perms, p0, (int)sc, w.zp, zd.bytes);
     } else if (split) {
