@@ -56,11 +56,13 @@ def _check(got, X, perms, I, J, mode):
 @pytest.mark.parametrize("mode", ["fp32", "split"])
 @pytest.mark.parametrize("n,l,P", [(300, 50, 40), (33, 7, 25), (600, 129, 12), (200, 96, 33),
                                    (150, 64, 5), (97, 512, 17), (2, 10, 7), (40, 64, 1),
-                                   (120, 300, 9)])
+                                   (120, 300, 9), (150, 131, 60)])
 def test_small_all_pairs(mode, n, l, P):
     """Every pair against the oracle.  In split the kernel streams the
     unpermuted rows in segments of 1, 2, 3 or 4 chunks of 32 samples, the
-    most that divide the row's chunks: l = 129, 300, 96 and 512 take each."""
+    most that divide the row's chunks: l = 129, 300, 96 and 512 take each.
+    Rows with l % 4 != 0 load their permutation indices one by one; l = 131
+    with P = 60 does so over three passes."""
     rng = np.random.default_rng(n + l + P)
     X, _ = workloads.planted(n, l, n, n_planted=5, dtype=np.float32)
     perms = np.stack([rng.permutation(l) for _ in range(P)]).astype(np.int32)
