@@ -101,11 +101,33 @@ def _signature(shapes: Sequence[tuple], mode_i: int) -> str:
     return f"batch|{_device_key()}|{mode_i}|{h}"
 
 
+def _tile_slots(n: int, t: int) -> int:
+    """Pair slots the tiles of width t compute for n profiles (whole tiles of
+    the inclusive triangle, padding rows included)."""
+    m = -(-n // t)
+    return m * (m + 1) // 2 * t * t
+
+
 def _assignments(shapes: Sequence[tuple]) -> Dict[str, List[int]]:
+    """Candidate tile widths per dataset: all one width, 128 below a size
+    threshold, or 128 where 256-wide tiles would compute a given share more
+    pair slots (padding rows and whole diagonal tiles), alone or with the
+    size rule."""
     out = {"all256": [256] * len(shapes), "all128": [128] * len(shapes)}
-    for thr in (1024, 2048, 4096):
+    for thr in (1024, 1536, 2048, 3072, 4096):
         out[f"128_below_{thr}"] = [128 if n < thr else 256 for n, _ in shapes]
-    return out
+    excess = [_tile_slots(n, 256) / _tile_slots(n, 128) - 1.0 for n, _ in shapes]
+    for x in (0.1, 0.2, 0.35):
+        out[f"128_over_{x:g}_excess"] = [128 if e > x else 256 for e in excess]
+        out[f"128_below_2048_or_over_{x:g}_excess"] = [
+            128 if (n < 2048 or e > x) else 256 for (n, _), e in zip(shapes, excess)]
+    # identical assignments are timed once
+    seen, uniq = set(), {}
+    for name, tiles in out.items():
+        if tuple(tiles) not in seen:
+            seen.add(tuple(tiles))
+            uniq[name] = tiles
+    return uniq
 
 
 def tune_batch(xs: Sequence, mode="split", reps: int = 3, use_cache: bool = True):
