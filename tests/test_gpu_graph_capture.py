@@ -82,3 +82,37 @@ def test_normalize_allpairs_edges_captured_and_replayed(mode):
         got = sorted(zip(ij.view(-1, 2)[:c_ref].cpu().numpy().tolist(), rv[:c_ref].cpu().numpy().tolist()))
         want = sorted(zip(ij_ref.cpu().numpy().reshape(-1, 2).tolist(), rv_ref.cpu().numpy().tolist()))
         assert got == want, rep
+
+
+@pytest.mark.parametrize("mode,l,tiles", [("split", 200, False), ("fp32", 200, False),
+                                          ("split", 1100, True)])
+def test_permtest_captured_and_replayed(mode, l, tiles):
+    """The permutation test recorded as one graph (the persistent LDS kernel,
+    or the tiled form's fills, observed r, gathers, tile launches and final
+    sum) and replayed: every replay gives the eager counts."""
+    import torch
+    import paper_1605_01584_amd as pcc
+    n, P = 300, 40
+    X, _ = workloads.planted(n, l, 33, n_planted=4, dtype=np.float32)
+    rng = np.random.default_rng(l)
+    perms = torch.from_numpy(np.stack([rng.permutation(l) for _ in range(P)]).astype(np.int32)).cuda()
+    z, zd = pcc.normalize(to_device(X), mode)
+    assert (zd.l_pad > pcc.permtest_max_l(mode)) == tiles
+    ws = torch.empty(max(pcc.workspace_size(zd, 2), 256), dtype=torch.uint8, device="cuda")
+    ref = pcc.permtest(z, zd, perms, workspace=ws)            # eager, rows checked
+    torch.cuda.synchronize()
+    c = torch.empty_like(ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            pcc.permtest(z, zd, perms, out=c, stream=s, validate=False, workspace=ws)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        c.fill_(-7)
+        ws.fill_(0x5a)                                           # the tiled form refills its slots
+        _ = (z.float() * 2).sum().item()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(c, ref), rep
