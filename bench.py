@@ -187,7 +187,7 @@ def main():
     ap.add_argument("--legs", default="all",
                     help="comma list of extra legs (normalize, fp32, modes16, edges, fp64, xy, to_host, "
                          "calibration, permtest, permtest_long, batched, big_edges, table1, config1, "
-                         "config2), default all")
+                         "config2; power, which samples the board power, only when named), default all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -196,7 +196,9 @@ def main():
     args = ap.parse_args()
 
     def want(leg):
-        return not args.no_extras and (args.legs == "all" or leg in args.legs.split(","))
+        if args.no_extras:
+            return False
+        return leg in args.legs.split(",") or (args.legs == "all" and leg not in OPT_IN_LEGS)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the all-pairs path "
                                    "is measured on a single MI355X (multi-GPU sharding is a "
@@ -494,8 +496,112 @@ def main():
         extras.update(bench_config1(pcc, workloads, stream, dev))
     if want("config2"):
         extras.update(bench_config2(pcc, workloads, stream, dev))
+    if want("power"):
+        extras.update(bench_power(pcc, workloads, stream, dev))
     out["extras"] = extras
     print(json.dumps(out), flush=True)
+
+
+# Legs that "--legs all" leaves out: run only when named.
+OPT_IN_LEGS = {"power"}
+
+
+def read_board_power():
+    """Socket power in W from amd-smi (or rocm-smi), or None.  The tools run
+    as child processes."""
+    import re
+    import subprocess
+    for cmd, pat in ((["amd-smi", "metric", "-p", "--json"], r'"socket_power"\s*:\s*\{\s*"value"\s*:\s*([0-9.]+)'),
+                     (["rocm-smi", "--showpower", "--json"], r'Power \(W\)"\s*:\s*"([0-9.]+)"')):
+        try:
+            txt = subprocess.run(cmd, capture_output=True, text=True, timeout=5).stdout
+        except (OSError, subprocess.SubprocessError):
+            continue
+        m = re.search(pat, txt)
+        if m:
+            return float(m.group(1))
+    return None
+
+
+def bench_power(pcc, workloads, stream, dev, secs=5.0):
+    """Board power while one kernel runs back to back for a few seconds: the
+    split and FP32 tiles on n = 32768, l = 4096, the register-only BF16 MFMA
+    probe, the split permutation test (n = 8192, l = 512, P = 1000) and the
+    uneven batch.  Median and largest of the samples after the first second
+    of each phase."""
+    import ctypes
+    import threading
+    import time
+    import torch
+    log("[bench] board power per kernel")
+    if read_board_power() is None:
+        return {"power": {"error": "no power reading from amd-smi or rocm-smi"}}
+    samples, stop = [], [False]
+
+    def sampler():
+        while not stop[0]:
+            w = read_board_power()
+            if w is not None:
+                samples.append((time.time(), w))
+            time.sleep(0.2)
+
+    th = threading.Thread(target=sampler, daemon=True)
+    th.start()
+    phases = []
+
+    def phase(name, fn):
+        t0, k = time.time(), 0
+        while time.time() - t0 < secs:
+            fn()
+            k += 1
+            if k % 10 == 0:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        phases.append((name, t0, time.time(), k))
+
+    try:
+        time.sleep(2.0)
+        phases.append(("idle", time.time() - 2.0, time.time(), 0))
+        x = torch.randn(32768, 4096, device=dev)
+        for mode in ("split", "fp32"):
+            z, zd = pcc.normalize(x, mode)
+            r = torch.empty(zd.n * (zd.n - 1) // 2, dtype=torch.float32, device=dev)
+            cfg = pcc.default_cfg(zd)
+            phase(f"{mode}_tiles", lambda: pcc.allpairs(z, zd, cfg, out=r))
+            del z, r
+        del x
+        torch.cuda.empty_cache()
+        lib = ctypes.CDLL(os.path.join(os.path.dirname(pcc.__file__), "libpcc_probe.so"))
+        lib.pcc_probe_mfma_bf16.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]
+        blocks = torch.cuda.get_device_properties(dev).multi_processor_count * 8
+        src = torch.randn(512, device=dev).to(torch.bfloat16)
+        sink = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+        phase("mfma_loop", lambda: lib.pcc_probe_mfma_bf16(
+            blocks, 20000, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(sink.data_ptr()),
+            ctypes.c_void_p(stream.cuda_stream)))
+        X, _, perms = workloads.config4()
+        z, zd = pcc.normalize(torch.from_numpy(X).to(dev), "split")
+        pt = torch.from_numpy(perms).to(dev)
+        c = torch.empty(zd.n * (zd.n - 1) // 2, dtype=torch.int32, device=dev)
+        pcc.permtest(z, zd, pt, out=c)                 # rows checked once
+        phase("permtest_split", lambda: pcc.permtest(z, zd, pt, out=c, validate=False))
+        del z, pt, c
+        batch = workloads.config5_batch()
+        xs = [torch.from_numpy(B).to(dev) for B, _ in batch]
+        plan = pcc.BatchPlan(xs, "split", tiles=[128 if B.shape[0] < 2048 else 256 for B, _ in batch])
+        phase("batch", plan.launch)
+        plan.close()
+    finally:
+        stop[0] = True
+        th.join()
+    out = {}
+    for name, t0, t1, k in phases:
+        ws = sorted(w for t, w in samples if t0 + (0.0 if name == "idle" else 1.0) <= t <= t1)
+        out[name] = {"calls": k, "ms_per_call": (t1 - t0) * 1e3 / k if k else None,
+                     "samples": len(ws), "median_W": ws[len(ws) // 2] if ws else None,
+                     "max_W": ws[-1] if ws else None}
+    return {"power": {"what": "socket power from amd-smi while each kernel runs back to back", **out}}
 
 
 # The paper's Table I: LightPCC in FP64 on one Xeon Phi 5110P, seconds for
