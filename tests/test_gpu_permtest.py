@@ -142,3 +142,21 @@ def test_config4_full_size_sampled(mode):
     assert np.all(g[-len(pl.u):] == 0)
     assert np.all((got >= 0) & (got <= 1000))
     print(f"{mode}: {loose} of {len(I)} sampled pairs with an undecided count")
+
+
+@pytest.mark.parametrize("mode", ["fp32", "split"])
+def test_ragged_n_full_P_sampled(mode):
+    """n = 1000 (not a multiple of the 64-row or 32-row jobs), l = 512,
+    P = 1000: every job runs all passes and the last tile row and column are
+    partial; 3000 seeded pairs against the oracle."""
+    rng = np.random.default_rng(77)
+    n, l, P = 1000, 512, 1000
+    X, pl = workloads.planted(n, l, 77, n_planted=6, dtype=np.float32)
+    perms = np.stack([rng.permutation(l) for _ in range(P)]).astype(np.int32)
+    got = _gpu_counts(X, perms, mode)
+    I, J = workloads.random_pairs(n, 3000, seed=78)
+    I = np.concatenate([I, np.minimum(pl.u, pl.v), [n - 2, 0]])
+    J = np.concatenate([J, np.maximum(pl.u, pl.v), [n - 1, n - 1]])
+    loose = _check(got[packed_pos(n, I, J)], X, perms, I, J, mode)
+    assert np.all((got >= 0) & (got <= P))
+    print(f"{mode}: {loose} of {len(I)} sampled pairs with an undecided count")
