@@ -5,8 +5,9 @@
   synthetic Z of exactly that shape (run time does not depend on the
   values), cached per (device, mode, n, l_pad).
 * ``tune_batch(xs, mode)``: the fastest per-dataset tile sizes for one
-  uneven batch.  Candidate assignments (all 256, all 128, and "128 below a
-  size threshold" rules) are built as batch plans and timed as whole graph
+  uneven batch.  Candidate assignments (all 256, all 128, "128 below a size
+  threshold" rules, and 128 where 256-wide tiles would compute a given share
+  more pair slots) are built as batch plans and timed as whole graph
   launches, since inside one persistent launch what matters is the sum of
   per-job costs and the balance of the shared job counter, not each
   dataset's stand-alone speed.  Cached per (device, mode, batch signature).
